@@ -1,0 +1,137 @@
+"""Reference oracle for bilinear resize and affine warp -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never loads it and
+the two share no code.
+
+The arithmetic lives in ``kro.c`` (plain C, binary64 / exact integers); this
+module only compiles it with gcc and marshals numpy arrays.  The definitions
+(half-pixel centres, exact-rational resize coordinates, the binary64 fma chain
+for the warp's inverse map, per-tap borders, 11-bit u8 weights) are stated in
+the header of ``kro.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kro.c")
+_LIB_PATH = os.path.join(_HERE, "libkro.so")
+_lib = None
+
+CONSTANT = 0
+REPLICATE = 1
+
+
+def build() -> str:
+    """Compile kro.c into oracle/libkro.so (always recompiles)."""
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    override = os.environ.get("KRO_LIB")  # a mutated build, for the pin-strength test
+    if override:
+        lib = ctypes.CDLL(override)
+    else:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.kro_resize.argtypes = [vp, i, i, i, i, vp, i, i, i, i, d, dp, dp, i]
+    lib.kro_resize.restype = i
+    lib.kro_warp.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, d, dp, dp, i]
+    lib.kro_warp.restype = i
+    lib.kro_invert_affine.argtypes = [dp, dp]
+    lib.kro_invert_affine.restype = i
+    _lib = lib
+    return lib
+
+
+def _src_args(src: np.ndarray):
+    if src.ndim == 2:
+        src = src[:, :, None]
+    if src.ndim != 3:
+        raise ValueError("src must be HxW or HxWxC")
+    src = np.ascontiguousarray(src)
+    if src.dtype == np.uint8:
+        st = 0
+    elif src.dtype == np.float32:
+        st = 1
+    else:
+        raise TypeError("src dtype must be uint8 or float32")
+    return src, st
+
+
+def _norm_args(mean, std, c):
+    if mean is None:
+        return None, None, None
+    m = (ctypes.c_double * 4)(*[float(v) for v in list(mean)[:c]] + [0.0] * (4 - c))
+    s = (ctypes.c_double * 4)(*[float(v) for v in list(std)[:c]] + [1.0] * (4 - c))
+    return m, s, (m, s)
+
+
+def resize(src: np.ndarray, dh: int, dw: int, out: str = "u8", border: int = REPLICATE,
+           bval: float = 0.0, mean=None, std=None, threads: int = 1) -> np.ndarray:
+    """Oracle bilinear resize.  ``out`` is "u8" (fixed-point path) or "f64"
+    (the f32 path's values, reported in binary64)."""
+    lib = _load()
+    src, st = _src_args(src)
+    h, w, c = src.shape
+    if out == "u8":
+        dst = np.zeros((dh, dw, c), np.uint8)
+        ot = 0
+    else:
+        dst = np.zeros((dh, dw, c), np.float64)
+        ot = 1
+    m, s, _keep = _norm_args(mean, std, c)
+    rc = lib.kro_resize(src.ctypes.data, h, w, c, st, dst.ctypes.data, dh, dw, ot,
+                        border, float(bval), m, s, threads)
+    if rc != 0:
+        raise ValueError("kro_resize rejected its arguments")
+    return dst
+
+
+def warp(src: np.ndarray, m6, dh: int, dw: int, out: str = "u8", inverse: bool = False,
+         border: int = CONSTANT, bval: float = 0.0, mean=None, std=None,
+         threads: int = 1) -> np.ndarray:
+    """Oracle bilinear affine warp.  ``m6`` is the row-major 2x3 matrix,
+    source->destination unless ``inverse``."""
+    lib = _load()
+    src, st = _src_args(src)
+    h, w, c = src.shape
+    if out == "u8":
+        dst = np.zeros((dh, dw, c), np.uint8)
+        ot = 0
+    else:
+        dst = np.zeros((dh, dw, c), np.float64)
+        ot = 1
+    mm = (ctypes.c_double * 6)(*[float(v) for v in np.asarray(m6, np.float64).reshape(6)])
+    nm, ns, _keep = _norm_args(mean, std, c)
+    rc = lib.kro_warp(src.ctypes.data, h, w, c, st, dst.ctypes.data, dh, dw, ot, mm,
+                      1 if inverse else 0, border, float(bval), nm, ns, threads)
+    if rc != 0:
+        raise ValueError("kro_warp rejected its arguments")
+    return dst
+
+
+def invert_affine(m6) -> np.ndarray:
+    """Inverse of a 2x3 affine map by the fixed formula in kro.c."""
+    lib = _load()
+    mm = (ctypes.c_double * 6)(*[float(v) for v in np.asarray(m6, np.float64).reshape(6)])
+    out = (ctypes.c_double * 6)()
+    if lib.kro_invert_affine(mm, out) != 0:
+        raise ValueError("singular affine matrix")
+    return np.array(list(out), np.float64)

@@ -1,0 +1,226 @@
+/*
+ * kro.c -- reference oracle for bilinear resize and affine warp (TEST
+ * INFRASTRUCTURE ONLY).
+ *
+ * This file is the plain, slow, obviously-correct CPU definition that the HIP
+ * kernels are checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product library never
+ * links or calls it, and it shares no code with the product.
+ *
+ * What it computes.  The paper (Sec. II-A, kornia-imgproc "geometric
+ * transforms"; Sec. III, the benchmarked up- and down-sizing operators;
+ * Sec. II-B.2, the interleaved Image<T, C> layout; Sec. II-B.4, caller-owned
+ * output buffers) names the operators but prints no formula.  The definitions
+ * below are the readings this project fixes for it:
+ *
+ *  - Images are HWC-contiguous, C interleaved channels, u8 or f32 samples.
+ *  - Resize uses half-pixel centres: source x = (dx + 1/2) * W_in / W_out - 1/2,
+ *    held as the exact rational num / den with num = (2 dx + 1) W_in - W_out,
+ *    den = 2 W_out, so floor and fraction are exact integers.
+ *  - Warp: the 2x3 matrix maps source to destination unless the caller says it
+ *    is already the inverse.  Pixel j's centre is at coordinate j.  The inverse
+ *    map is evaluated per destination pixel as xs = fma(A, x, fma(B, y, C)),
+ *    ys = fma(D, x, fma(E, y, F)) in IEEE binary64 with correctly rounded fma,
+ *    and clamped to [-2, W+1] x [-2, H+1] (beyond that every tap is a border
+ *    tap either way).
+ *  - Borders are handled per tap: a tap outside the image is the constant b
+ *    (CONSTANT) or the nearest edge pixel (REPLICATE).  Weights always come
+ *    from the unclamped coordinate.
+ *  - u8 output: 11-bit per-axis weights w1 = round-half-even(2048 * frac),
+ *    w0 = 2048 - w1; acc = sum wy_i * wx_j * p_ij exactly in integers;
+ *    out = floor((acc + 2^21) / 2^22).
+ *  - f32 output: the same taps with unquantised binary64 weights (1 - f, f),
+ *    on the 0..255 scale; optionally normalised per channel as
+ *    (v / 255 - mean_c) / std_c.  The oracle reports these values in binary64.
+ *
+ * Parity status: every function here is pinned by the tests in
+ * tests/test_oracle.py (closed forms, exact permutations, an exact-rational
+ * brute force and library cross-checks); none is "parity unpinned".
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -fPIC -shared kro.c -lm
+ * (-ffp-contract=off so that no product/sum pair is silently fused.)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+enum { KRO_U8 = 0, KRO_F32 = 1 };        /* source sample types */
+enum { KRO_OUT_U8 = 0, KRO_OUT_F64 = 1 }; /* oracle output types */
+enum { KRO_CONSTANT = 0, KRO_REPLICATE = 1 };
+
+/* floor(a / b) for b > 0 and any sign of a. */
+static int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b) != 0 && a < 0)
+        q -= 1;
+    return q;
+}
+
+/* round-half-even(2048 * r / den) for 0 <= r < den, in exact integers.
+ * 2048 r / den + 1/2 = (4096 r + den) / (2 den); its floor rounds half up,
+ * and a tie (exact division) is moved down to the even neighbour. */
+static int64_t weight_from_ratio(int64_t r, int64_t den)
+{
+    int64_t t = 4096 * r + den;
+    int64_t q = t / (2 * den);
+    if (t % (2 * den) == 0 && (q & 1))
+        q -= 1;
+    return q;
+}
+
+/* One source sample at integer position (x, y), channel ch, with the border
+ * rule applied to this tap alone. */
+static double tap(const void *src, int src_t, int h, int w, int c,
+                  int64_t x, int64_t y, int ch, int border, double bval)
+{
+    if (x < 0 || x >= w || y < 0 || y >= h) {
+        if (border == KRO_CONSTANT)
+            return bval;
+        if (x < 0) x = 0;
+        if (x >= w) x = w - 1;
+        if (y < 0) y = 0;
+        if (y >= h) y = h - 1;
+    }
+    size_t idx = ((size_t)y * (size_t)w + (size_t)x) * (size_t)c + (size_t)ch;
+    if (src_t == KRO_U8)
+        return (double)((const uint8_t *)src)[idx];
+    return (double)((const float *)src)[idx];
+}
+
+/* Integer tap for the u8 path (CONSTANT b is an integer in [0, 255]). */
+static int64_t tap_u8(const uint8_t *src, int h, int w, int c,
+                      int64_t x, int64_t y, int ch, int border, int64_t bval)
+{
+    if (x < 0 || x >= w || y < 0 || y >= h) {
+        if (border == KRO_CONSTANT)
+            return bval;
+        if (x < 0) x = 0;
+        if (x >= w) x = w - 1;
+        if (y < 0) y = 0;
+        if (y >= h) y = h - 1;
+    }
+    return src[((size_t)y * (size_t)w + (size_t)x) * (size_t)c + (size_t)ch];
+}
+
+/* Writes one output pixel, given the top-left tap (x0, y0) and the per-axis
+ * weights: integer 11-bit weights for u8 output, binary64 fractions fx, fy
+ * for f64 output. */
+static void write_pixel(const void *src, int src_t, int sh, int sw, int c,
+                        void *dst, int out_t, size_t didx,
+                        int64_t x0, int64_t y0, int64_t wx1, int64_t wy1,
+                        double fx, double fy, int border, double bval,
+                        const double *mean, const double *stdv)
+{
+    for (int ch = 0; ch < c; ch++) {
+        if (out_t == KRO_OUT_U8) {
+            const uint8_t *s = (const uint8_t *)src;
+            int64_t b = (int64_t)bval;
+            int64_t wx0 = 2048 - wx1, wy0 = 2048 - wy1;
+            int64_t acc = wy0 * wx0 * tap_u8(s, sh, sw, c, x0, y0, ch, border, b)
+                        + wy0 * wx1 * tap_u8(s, sh, sw, c, x0 + 1, y0, ch, border, b)
+                        + wy1 * wx0 * tap_u8(s, sh, sw, c, x0, y0 + 1, ch, border, b)
+                        + wy1 * wx1 * tap_u8(s, sh, sw, c, x0 + 1, y0 + 1, ch, border, b);
+            ((uint8_t *)dst)[didx + (size_t)ch] = (uint8_t)((acc + (1 << 21)) >> 22);
+        } else {
+            double v = (1.0 - fy) * (1.0 - fx) * tap(src, src_t, sh, sw, c, x0, y0, ch, border, bval)
+                     + (1.0 - fy) * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0, ch, border, bval)
+                     + fy * (1.0 - fx) * tap(src, src_t, sh, sw, c, x0, y0 + 1, ch, border, bval)
+                     + fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0 + 1, ch, border, bval);
+            if (mean && stdv)
+                v = (v / 255.0 - mean[ch]) / stdv[ch];
+            ((double *)dst)[didx + (size_t)ch] = v;
+        }
+    }
+}
+
+/* Bilinear resize with half-pixel centres.  Returns 0, or -1 on bad sizes. */
+int kro_resize(const void *src, int sh, int sw, int c, int src_t,
+               void *dst, int dh, int dw, int out_t,
+               int border, double bval, const double *mean, const double *stdv,
+               int nthreads)
+{
+    if (sh < 1 || sw < 1 || dh < 1 || dw < 1 || c < 1 || c > 4)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int dy = 0; dy < dh; dy++) {
+        int64_t ny = (int64_t)(2 * dy + 1) * sh - dh, deny = 2 * (int64_t)dh;
+        int64_t y0 = floor_div(ny, deny), ry = ny - y0 * deny;
+        for (int dx = 0; dx < dw; dx++) {
+            int64_t nx = (int64_t)(2 * dx + 1) * sw - dw, denx = 2 * (int64_t)dw;
+            int64_t x0 = floor_div(nx, denx), rx = nx - x0 * denx;
+            write_pixel(src, src_t, sh, sw, c, dst, out_t,
+                        ((size_t)dy * (size_t)dw + (size_t)dx) * (size_t)c,
+                        x0, y0, weight_from_ratio(rx, denx), weight_from_ratio(ry, deny),
+                        (double)rx / (double)denx, (double)ry / (double)deny,
+                        border, bval, mean, stdv);
+        }
+    }
+    return 0;
+}
+
+/* Inverse of the 2x3 affine map [[a, b, c], [d, e, f]] (rows of x' and y'),
+ * by the fixed formula: det = a e - b d (two products, one difference);
+ * A = e / det, B = -b / det, D = -d / det, E = a / det;
+ * C = -(A c + B f), F = -(D c + E f).  Returns -1 if det is zero or not
+ * finite. */
+int kro_invert_affine(const double m[6], double inv[6])
+{
+    double p1 = m[0] * m[4];
+    double p2 = m[1] * m[3];
+    double det = p1 - p2;
+    if (det == 0.0 || !isfinite(det))
+        return -1;
+    double A = m[4] / det, B = -m[1] / det, D = -m[3] / det, E = m[0] / det;
+    double t1 = A * m[2], t2 = B * m[5];
+    double C = -(t1 + t2);
+    double t3 = D * m[2], t4 = E * m[5];
+    double F = -(t3 + t4);
+    inv[0] = A; inv[1] = B; inv[2] = C;
+    inv[3] = D; inv[4] = E; inv[5] = F;
+    return 0;
+}
+
+/* Bilinear affine warp.  m is source->destination unless inverse != 0, in
+ * which case it already maps destination pixel centres to source coordinates.
+ * Returns 0, or -1 on bad sizes or a singular matrix. */
+int kro_warp(const void *src, int sh, int sw, int c, int src_t,
+             void *dst, int dh, int dw, int out_t,
+             const double m[6], int inverse,
+             int border, double bval, const double *mean, const double *stdv,
+             int nthreads)
+{
+    if (sh < 1 || sw < 1 || dh < 1 || dw < 1 || c < 1 || c > 4)
+        return -1;
+    double im[6];
+    if (inverse) {
+        for (int i = 0; i < 6; i++)
+            im[i] = m[i];
+    } else if (kro_invert_affine(m, im) != 0) {
+        return -1;
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int y = 0; y < dh; y++) {
+        for (int x = 0; x < dw; x++) {
+            double xs = fma(im[0], (double)x, fma(im[1], (double)y, im[2]));
+            double ys = fma(im[3], (double)x, fma(im[4], (double)y, im[5]));
+            if (xs < -2.0) xs = -2.0;
+            if (xs > (double)sw + 1.0) xs = (double)sw + 1.0;
+            if (ys < -2.0) ys = -2.0;
+            if (ys > (double)sh + 1.0) ys = (double)sh + 1.0;
+            double fx0 = floor(xs), fy0 = floor(ys);
+            double fx = xs - fx0, fy = ys - fy0;
+            int64_t wx1 = (int64_t)nearbyint(2048.0 * fx);
+            int64_t wy1 = (int64_t)nearbyint(2048.0 * fy);
+            write_pixel(src, src_t, sh, sw, c, dst, out_t,
+                        ((size_t)y * (size_t)dw + (size_t)x) * (size_t)c,
+                        (int64_t)fx0, (int64_t)fy0, wx1, wy1, fx, fy,
+                        border, bval, mean, stdv);
+        }
+    }
+    return 0;
+}

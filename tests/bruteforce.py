@@ -1,0 +1,98 @@
+"""Exact-rational brute force of the resampling definitions (test-only).
+
+Written independently of the C oracle: every coordinate, weight and blend is
+carried in ``fractions.Fraction``; a binary64 fma is emulated as the correctly
+rounded conversion of the exact a*x + t (``float(Fraction)`` rounds to
+nearest-even).  Python float arithmetic is IEEE binary64 without contraction,
+so the fixed inverse-map formula is reproduced operation by operation.  Meant
+for inputs up to about 64x64.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+
+def fma(a: float, x: float, t: float) -> float:
+    return float(Fraction(a) * Fraction(x) + Fraction(t))
+
+
+def rne(q: Fraction) -> int:
+    """Round a rational to the nearest integer, ties to even (Python's round)."""
+    return round(q)
+
+
+def invert_affine(m):
+    a, b, c, d, e, f = [float(v) for v in np.asarray(m, np.float64).reshape(6)]
+    det = a * e - b * d
+    A, B, D, E = e / det, -b / det, -d / det, a / det
+    C = -(A * c + B * f)
+    F = -(D * c + E * f)
+    return (A, B, C, D, E, F)
+
+
+def _tap(src, x, y, ch, border, bval):
+    h, w = src.shape[0], src.shape[1]
+    if 0 <= x < w and 0 <= y < h:
+        return Fraction(src[y, x, ch].item())
+    if border == 0:
+        return Fraction(bval)
+    return Fraction(src[min(max(y, 0), h - 1), min(max(x, 0), w - 1), ch].item())
+
+
+def _blend(src, x0, y0, fx: Fraction, fy: Fraction, out, border, bval, mean, std):
+    c = src.shape[2]
+    res = []
+    for ch in range(c):
+        taps = [[_tap(src, x0 + j, y0 + i, ch, border, bval) for j in (0, 1)] for i in (0, 1)]
+        if out == "u8":
+            wx1 = rne(2048 * fx)
+            wy1 = rne(2048 * fy)
+            wx = (2048 - wx1, wx1)
+            wy = (2048 - wy1, wy1)
+            acc = sum(wy[i] * wx[j] * taps[i][j] for i in (0, 1) for j in (0, 1))
+            res.append(math.floor((acc + 2 ** 21) / Fraction(2 ** 22)))
+        else:
+            wx = (1 - fx, fx)
+            wy = (1 - fy, fy)
+            v = sum(wy[i] * wx[j] * taps[i][j] for i in (0, 1) for j in (0, 1))
+            if mean is not None:
+                v = (v / 255 - Fraction(mean[ch])) / Fraction(std[ch])
+            res.append(float(v))
+    return res
+
+
+def resize(src: np.ndarray, dh: int, dw: int, out="u8", border=1, bval=0, mean=None, std=None):
+    """Half-pixel-centre bilinear resize: source x = (dx + 1/2) W/dw - 1/2 exactly."""
+    h, w, c = src.shape
+    dst = np.zeros((dh, dw, c), np.uint8 if out == "u8" else np.float64)
+    for dy in range(dh):
+        ys = (Fraction(2 * dy + 1, 2)) * Fraction(h, dh) - Fraction(1, 2)
+        y0 = math.floor(ys)
+        for dx in range(dw):
+            xs = (Fraction(2 * dx + 1, 2)) * Fraction(w, dw) - Fraction(1, 2)
+            x0 = math.floor(xs)
+            dst[dy, dx, :] = _blend(src, x0, y0, xs - x0, ys - y0, out, border, bval, mean, std)
+    return dst
+
+
+def warp(src: np.ndarray, m, dh: int, dw: int, out="u8", inverse=False, border=0, bval=0,
+         mean=None, std=None):
+    """Affine warp: per destination pixel centre (x, y), xs = fma(A, x, fma(B, y, C)),
+    ys = fma(D, x, fma(E, y, F)) in binary64, clamped to [-2, W+1] x [-2, H+1]."""
+    h, w, c = src.shape
+    A, B, C, D, E, F = ([float(v) for v in np.asarray(m, np.float64).reshape(6)] if inverse
+                        else invert_affine(m))
+    dst = np.zeros((dh, dw, c), np.uint8 if out == "u8" else np.float64)
+    for y in range(dh):
+        for x in range(dw):
+            xs = fma(A, float(x), fma(B, float(y), C))
+            ys = fma(D, float(x), fma(E, float(y), F))
+            xs = min(max(xs, -2.0), w + 1.0)
+            ys = min(max(ys, -2.0), h + 1.0)
+            fxs, fys = Fraction(xs), Fraction(ys)
+            x0, y0 = math.floor(fxs), math.floor(fys)
+            dst[y, x, :] = _blend(src, x0, y0, fxs - x0, fys - y0, out, border, bval, mean, std)
+    return dst
