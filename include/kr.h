@@ -1,0 +1,178 @@
+/*
+ * kr.h -- C ABI of libkr, MI355X (gfx950) bilinear resampling kernels.
+ *
+ * The operators are the image-transformation hot path of kornia-rs
+ * (arXiv 2505.12425): resize up and down (Sec. III, the benchmarked
+ * "geometric transformations"), affine warping (Sec. II-A, kornia-imgproc
+ * "geometric transforms"), on interleaved Image<T, C> buffers (Sec. II-B.2),
+ * with caller-owned, pre-allocated outputs and no allocation on the call path
+ * (Sec. II-B.4 and the "no implicit allocations" point of Listing 1).
+ * The paper prints no resampling formula; the definitions fixed here are:
+ *
+ *  - layout: HWC-contiguous, C interleaved channels (1 <= C <= 4), row pitch
+ *    W*C elements, u8 or f32 samples;
+ *  - half-pixel centres: resize source x = (dx + 1/2) * W_in / W_out - 1/2,
+ *    evaluated exactly as a rational; warp destination pixel (x, y) maps to
+ *    xs = fma(A, x, fma(B, y, C)), ys = fma(D, x, fma(E, y, F)) in binary64,
+ *    where [[A, B, C], [D, E, F]] is the inverse map;
+ *  - per-tap borders: a tap outside the source reads the constant border value
+ *    (KR_BORDER_CONSTANT) or the nearest edge pixel (KR_BORDER_REPLICATE);
+ *  - u8 output: 11-bit per-axis weights w1 = round-half-even(2048 * frac),
+ *    w0 = 2048 - w1, exact integer sum, out = (acc + 2^21) >> 22;
+ *  - f32 output: unquantised weights, values on the 0..255 scale, optionally
+ *    normalised per channel as (v / 255 - mean_c) / std_c.
+ *
+ * Conventions shared by every entry point:
+ *  - src, dst, workspace are DEVICE pointers, 16-byte aligned, owned by the
+ *    caller; the library never frees or retains them.  src and dst must not
+ *    overlap.
+ *  - stream is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued asynchronously; the call returns once it is enqueued.
+ *  - Arguments are validated synchronously before anything is enqueued; on a
+ *    validation failure nothing is enqueued and a kr_status other than KR_OK
+ *    is returned.  kr_last_error() then describes it (per calling thread).
+ *  - Launch failures return KR_ERR_HIP.  Faults during execution surface at
+ *    the caller's next synchronisation, as for any HIP kernel.
+ *  - Sizes: 1 <= H, W <= 32767.  Supported (src, dst) types: (U8, U8),
+ *    (U8, F32), (F32, F32).  norm is only accepted with an F32 destination.
+ *    For a U8 source the border value must be an integer in [0, 255].
+ *  - All entry points are reentrant; no C++ exception crosses the ABI.
+ */
+#ifndef KR_H
+#define KR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KR_OK = 0,
+    KR_ERR_INVALID_ARGUMENT = 1, /* null/misaligned pointer, bad size, overlap, bad border value */
+    KR_ERR_UNSUPPORTED = 2,      /* dtype pair, channel count or border mode not provided */
+    KR_ERR_SINGULAR_MATRIX = 3,  /* non-finite or (numerically) singular affine matrix */
+    KR_ERR_WORKSPACE_TOO_SMALL = 4,
+    KR_ERR_OUT_OF_BUDGET = 5,    /* a request larger than the serving memory budget */
+    KR_ERR_HIP = 6               /* a HIP runtime call failed */
+} kr_status;
+
+typedef enum { KR_U8 = 0, KR_F32 = 1 } kr_dtype;
+
+typedef enum { KR_BORDER_CONSTANT = 0, KR_BORDER_REPLICATE = 1 } kr_border;
+
+/* Per-channel normalisation on the [0, 1] scale: out_c = (v / 255 - mean[c]) / std[c].
+ * Only the first C entries are read.  std[c] must be finite and non-zero. */
+typedef struct {
+    float mean[4];
+    float std[4];
+} kr_normalize;
+
+/* kr_warp_affine / batch item flag: m is already the inverse map
+ * (destination pixel centre -> source coordinate). */
+#define KR_WARP_INVERSE_MAP 1
+
+/*
+ * Bilinear resize of one image (Sec. III "upsizing" and "downsizing").
+ * src: src_h x src_w x c samples of type src_t.  dst: dst_h x dst_w x c
+ * samples of type dst_t; the destination size is the target size (the
+ * paper's ops take a pre-sized output, Sec. IV-B/IV-C listings).
+ * border / border_value: tap rule for taps outside the source (only reached
+ * when upsampling; OpenCV-style resizes use KR_BORDER_REPLICATE).
+ * norm: NULL, or per-channel normalisation (F32 destination only).
+ */
+kr_status kr_resize_bilinear(const void *src, int src_h, int src_w, int c, kr_dtype src_t,
+                             void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                             kr_border border, float border_value, const kr_normalize *norm,
+                             void *stream);
+
+/*
+ * Bilinear affine warp of one image (Sec. II-A geometric transforms).
+ * m: HOST pointer to the row-major 2x3 matrix [[a, b, c], [d, e, f]].  It
+ * maps source to destination unless flags contains KR_WARP_INVERSE_MAP.  A
+ * forward matrix is inverted on the host by kr_invert_affine().
+ * Every destination pixel is written: taps outside the source follow border.
+ * Returns KR_ERR_SINGULAR_MATRIX for a non-finite matrix or, for a forward
+ * matrix, |det| <= 1e-12 * max(|a|, |b|, |d|, |e|)^2.
+ */
+kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype src_t,
+                         void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                         const double m[6], int flags,
+                         kr_border border, float border_value, const kr_normalize *norm,
+                         void *stream);
+
+/* One image of a batch.  op: 0 = resize, 1 = warp.  m and flags are read for
+ * warps only (same meaning as in kr_warp_affine). */
+typedef struct {
+    int op;
+    const void *src;
+    int src_h, src_w;
+    void *dst;
+    int dst_h, dst_w;
+    double m[6];
+    int flags;
+} kr_batch_item;
+
+#define KR_OP_RESIZE 0
+#define KR_OP_WARP 1
+
+/* Device workspace bytes kr_resize_batch needs for n items. */
+size_t kr_resize_batch_workspace_size(int n);
+
+/*
+ * Many resizes and warps of uneven sizes in ONE persistent launch over a
+ * work-list of output tiles (the batched form of the operators above).
+ * items: HOST array of n items, all with c channels and types (src_t, dst_t);
+ * border, border_value and norm apply to every item.  workspace: DEVICE
+ * buffer of at least kr_resize_batch_workspace_size(n) bytes, owned by the
+ * caller and not touched by other work until the batch completes.  Each
+ * item's output is bit-identical to the single-image call on the same item.
+ * Destinations must not overlap each other or any source.
+ */
+kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                          kr_border border, float border_value, const kr_normalize *norm,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * A reusable batch: kr_batch_plan_create validates the items, builds the
+ * work-list once (it allocates and fills its own device memory, synchronously)
+ * and captures {counter reset, persistent kernel} into a HIP graph.
+ * kr_batch_plan_launch replays that graph on stream.  Source and destination
+ * buffers named by the items must stay valid while the plan is used.
+ * kr_batch_plan_destroy frees the plan (after synchronising its last launch);
+ * NULL is ignored.
+ */
+typedef struct kr_batch_plan kr_batch_plan;
+kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtype src_t,
+                               kr_dtype dst_t, kr_border border, float border_value,
+                               const kr_normalize *norm, kr_batch_plan **plan);
+kr_status kr_batch_plan_launch(kr_batch_plan *plan, void *stream);
+void kr_batch_plan_destroy(kr_batch_plan *plan);
+
+/*
+ * Inverse of the 2x3 affine map m (host arrays, row-major) by the fixed
+ * formula: det = a*e - b*d (two rounded products, one rounded difference);
+ * A = e/det, B = -b/det, D = -d/det, E = a/det; C = -(A*c + B*f),
+ * F = -(D*c + E*f).  Same singularity rule as kr_warp_affine.
+ */
+kr_status kr_invert_affine(const double m[6], double inv[6]);
+
+/* Static text for a status code. */
+const char *kr_status_string(kr_status s);
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char *kr_last_error(void);
+
+/*
+ * Plain device-to-device copy of `bytes` bytes with 16-byte vector loads and
+ * stores: the HBM-bandwidth ceiling probe the resampling kernels are measured
+ * against.  dst and src must be 16-byte aligned and must not overlap.
+ */
+kr_status kr_hbm_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KR_H */

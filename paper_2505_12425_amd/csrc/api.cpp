@@ -1,0 +1,232 @@
+// api.cpp -- libkr's C ABI for single images: argument validation, the
+// inverse affine map, epilogue setup and dispatch to the kernels.
+//
+// Compiled with -ffp-contract=off: kr_invert_affine's formula must round each
+// product and sum on its own, exactly as written.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kr_api_internal.h"
+
+namespace kr {
+
+static thread_local std::string g_last_error;
+
+kr_status fail(kr_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static size_t elem_size(kr_dtype t) { return t == KR_U8 ? 1 : 4; }
+
+kr_status check_image(const char *what, const void *p, int h, int w, int c)
+{
+    if (!p)
+        return fail(KR_ERR_INVALID_ARGUMENT, "%s pointer is NULL", what);
+    if (reinterpret_cast<uintptr_t>(p) % 16 != 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "%s pointer is not 16-byte aligned", what);
+    if (h < 1 || w < 1 || h > KR_MAX_DIM || w > KR_MAX_DIM)
+        return fail(KR_ERR_INVALID_ARGUMENT, "%s size %dx%d outside [1, %d]", what, h, w, KR_MAX_DIM);
+    (void)c;
+    return KR_OK;
+}
+
+kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void *dst, int dh, int dw,
+                       kr_dtype dt, kr_border border, float bval, const kr_normalize *norm)
+{
+    if (c < 1 || c > 4)
+        return fail(KR_ERR_UNSUPPORTED, "channel count %d not in [1, 4]", c);
+    if (!((st == KR_U8 && dt == KR_U8) || (st == KR_U8 && dt == KR_F32) || (st == KR_F32 && dt == KR_F32)))
+        return fail(KR_ERR_UNSUPPORTED, "dtype pair (%d -> %d) not supported", (int)st, (int)dt);
+    if (border != KR_BORDER_CONSTANT && border != KR_BORDER_REPLICATE)
+        return fail(KR_ERR_UNSUPPORTED, "border mode %d not supported", (int)border);
+    kr_status s = check_image("src", src, sh, sw, c);
+    if (s != KR_OK)
+        return s;
+    s = check_image("dst", dst, dh, dw, c);
+    if (s != KR_OK)
+        return s;
+    if (!std::isfinite(bval))
+        return fail(KR_ERR_INVALID_ARGUMENT, "border value is not finite");
+    if (st == KR_U8 && (bval < 0.0f || bval > 255.0f || bval != std::floor(bval)))
+        return fail(KR_ERR_INVALID_ARGUMENT, "u8 border value %g is not an integer in [0, 255]", (double)bval);
+    if (norm) {
+        if (dt != KR_F32)
+            return fail(KR_ERR_INVALID_ARGUMENT, "normalisation needs an f32 destination");
+        for (int i = 0; i < c; i++)
+            if (!std::isfinite(norm->mean[i]) || !std::isfinite(norm->std[i]) || norm->std[i] == 0.0f)
+                return fail(KR_ERR_INVALID_ARGUMENT, "normalisation channel %d has a bad mean/std", i);
+    }
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(src);
+    const uintptr_t s1 = s0 + (uintptr_t)sh * (uintptr_t)sw * (uintptr_t)c * elem_size(st);
+    const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst);
+    const uintptr_t d1 = d0 + (uintptr_t)dh * (uintptr_t)dw * (uintptr_t)c * elem_size(dt);
+    if (s0 < d1 && d0 < s1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src and dst overlap");
+    return KR_OK;
+}
+
+Epilogue make_epilogue(int c, kr_border border, float bval, const kr_normalize *norm)
+{
+    Epilogue e;
+    std::memset(&e, 0, sizeof e);
+    for (int i = 0; i < 4; i++) {
+        e.alpha[i] = 1.0f;
+        e.beta[i] = 0.0f;
+    }
+    if (norm) {
+        for (int i = 0; i < c; i++) {
+            const double sd = (double)norm->std[i];
+            e.alpha[i] = (float)(1.0 / (255.0 * sd));
+            e.beta[i] = (float)(-(double)norm->mean[i] / sd);
+        }
+    }
+    e.bval_f = bval;
+    e.bval_i = (int)bval;
+    e.border = (int)border;
+    return e;
+}
+
+kr_status check_matrix(const double m[6], int flags, double inv[6])
+{
+    if (!m)
+        return fail(KR_ERR_INVALID_ARGUMENT, "matrix pointer is NULL");
+    for (int i = 0; i < 6; i++)
+        if (!std::isfinite(m[i]))
+            return fail(KR_ERR_SINGULAR_MATRIX, "matrix entry %d is not finite", i);
+    if (flags & KR_WARP_INVERSE_MAP) {
+        for (int i = 0; i < 6; i++)
+            inv[i] = m[i];
+        return KR_OK;
+    }
+    return invert_affine_impl(m, inv);
+}
+
+kr_status invert_affine_impl(const double m[6], double inv[6])
+{
+    const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+    double mx = std::fabs(a);
+    mx = std::fmax(mx, std::fabs(b));
+    mx = std::fmax(mx, std::fabs(d));
+    mx = std::fmax(mx, std::fabs(e));
+    const double p1 = a * e;
+    const double p2 = b * d;
+    const double det = p1 - p2;
+    if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * mx * mx || det == 0.0)
+        return fail(KR_ERR_SINGULAR_MATRIX, "affine matrix is singular (det = %g)", det);
+    const double A = e / det, B = -b / det, D = -d / det, E = a / det;
+    const double t1 = A * c, t2 = B * f;
+    const double C = -(t1 + t2);
+    const double t3 = D * c, t4 = E * f;
+    const double F = -(t3 + t4);
+    if (!std::isfinite(A) || !std::isfinite(B) || !std::isfinite(C) || !std::isfinite(D) ||
+        !std::isfinite(E) || !std::isfinite(F))
+        return fail(KR_ERR_SINGULAR_MATRIX, "inverse of the affine matrix is not finite");
+    inv[0] = A; inv[1] = B; inv[2] = C;
+    inv[3] = D; inv[4] = E; inv[5] = F;
+    return KR_OK;
+}
+
+}  // namespace kr
+
+using namespace kr;
+
+extern "C" {
+
+kr_status kr_resize_bilinear(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
+                             int dst_h, int dst_w, kr_dtype dst_t, kr_border border, float border_value,
+                             const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    if (s != KR_OK)
+        return s;
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    const hipError_t err = launch_resize(c, src_t, dst_t, j, e, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "resize launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
+kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
+                         int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags,
+                         kr_border border, float border_value, const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    if (s != KR_OK)
+        return s;
+    if (flags & ~KR_WARP_INVERSE_MAP)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown warp flags 0x%x", flags);
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    s = check_matrix(m, flags, j.inv);
+    if (s != KR_OK)
+        return s;
+    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    const hipError_t err = launch_warp(c, src_t, dst_t, j, e, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "warp launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
+kr_status kr_invert_affine(const double m[6], double inv[6])
+{
+    clear_error();
+    if (!m || !inv)
+        return fail(KR_ERR_INVALID_ARGUMENT, "NULL matrix pointer");
+    for (int i = 0; i < 6; i++)
+        if (!std::isfinite(m[i]))
+            return fail(KR_ERR_SINGULAR_MATRIX, "matrix entry %d is not finite", i);
+    return invert_affine_impl(m, inv);
+}
+
+const char *kr_status_string(kr_status s)
+{
+    switch (s) {
+    case KR_OK: return "ok";
+    case KR_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case KR_ERR_UNSUPPORTED: return "unsupported";
+    case KR_ERR_SINGULAR_MATRIX: return "singular matrix";
+    case KR_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case KR_ERR_OUT_OF_BUDGET: return "out of budget";
+    case KR_ERR_HIP: return "HIP error";
+    }
+    return "unknown status";
+}
+
+const char *kr_last_error(void) { return g_last_error.c_str(); }
+
+kr_status kr_hbm_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    clear_error();
+    if (!dst || !src)
+        return fail(KR_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+        return fail(KR_ERR_INVALID_ARGUMENT, "copy pointers must be 16-byte aligned");
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+    if (s0 < d0 + bytes && d0 < s0 + bytes)
+        return fail(KR_ERR_INVALID_ARGUMENT, "copy ranges overlap");
+    if (bytes == 0)
+        return KR_OK;
+    const hipError_t err = launch_copy(dst, src, bytes, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "copy launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
+}  // extern "C"

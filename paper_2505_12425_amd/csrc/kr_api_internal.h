@@ -1,0 +1,22 @@
+// kr_api_internal.h -- host-side helpers shared by libkr's ABI translation
+// units (validation, error state, parameter setup).
+#pragma once
+
+#include <cstdarg>
+
+#include "kr_internal.h"
+
+namespace kr {
+
+constexpr int KR_MAX_DIM = 32767;
+
+kr_status fail(kr_status s, const char *fmt, ...);
+void clear_error();
+kr_status check_image(const char *what, const void *p, int h, int w, int c);
+kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void *dst, int dh, int dw,
+                       kr_dtype dt, kr_border border, float bval, const kr_normalize *norm);
+Epilogue make_epilogue(int c, kr_border border, float bval, const kr_normalize *norm);
+kr_status check_matrix(const double m[6], int flags, double inv[6]);
+kr_status invert_affine_impl(const double m[6], double inv[6]);
+
+}  // namespace kr

@@ -1,0 +1,42 @@
+// kr_internal.h -- parameter blocks shared by libkr's host code and kernels.
+// Not part of the public ABI (include/kr.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "kr.h"
+
+namespace kr {
+
+enum { OP_RESIZE = 0, OP_WARP = 1 };
+
+// Output/epilogue parameters common to every kernel variant.
+struct Epilogue {
+    float alpha[4];  // f32 output: out_c = v * alpha[c] + beta[c] (1, 0 without normalisation)
+    float beta[4];
+    float bval_f;    // CONSTANT border value as a sample (f32 path)
+    int bval_i;      // CONSTANT border value as an integer sample (u8 path)
+    int border;      // KR_BORDER_CONSTANT or KR_BORDER_REPLICATE
+};
+
+// One image as the kernels see it.  For warps, inv is the inverse map with
+// its first row and second row kept as given (not pre-scaled).
+struct ImageJob {
+    const void *src;
+    void *dst;
+    int sh, sw, dh, dw;
+    double inv[6];
+};
+
+// Launchers (resample.hip).  All return the HIP error of the launch.
+hipError_t launch_generic(int op, int c, kr_dtype st, kr_dtype dt, const ImageJob &j,
+                          const Epilogue &e, hipStream_t s);
+hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
+                         hipStream_t s);
+hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
+                       hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+}  // namespace kr

@@ -1,0 +1,185 @@
+"""Thin ctypes binding over libkr.so (include/kr.h).
+
+Argument marshalling only: every step of resampling runs in the library's HIP
+kernels.  torch tensors supply device memory and streams.  The library is
+loaded on first use; if it has not been built this raises ``KrError`` -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkr.so")
+
+# kr_status
+OK = 0
+ERR_INVALID_ARGUMENT = 1
+ERR_UNSUPPORTED = 2
+ERR_SINGULAR_MATRIX = 3
+ERR_WORKSPACE_TOO_SMALL = 4
+ERR_OUT_OF_BUDGET = 5
+ERR_HIP = 6
+# kr_dtype
+U8 = 0
+F32 = 1
+# kr_border
+CONSTANT = 0
+REPLICATE = 1
+# flags / ops
+WARP_INVERSE_MAP = 1
+OP_RESIZE = 0
+OP_WARP = 1
+
+
+class KrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"kr status {status}: {message}")
+        self.status = status
+
+
+class Normalize(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_float * 4), ("std", ctypes.c_float * 4)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("src", ctypes.c_void_p), ("src_h", ctypes.c_int),
+                ("src_w", ctypes.c_int), ("dst", ctypes.c_void_p), ("dst_h", ctypes.c_int),
+                ("dst_w", ctypes.c_int), ("m", ctypes.c_double * 6), ("flags", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libkr.so with argument types declared."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise KrError(-1, f"{LIB_PATH} is not built; run `python -m paper_2505_12425_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, f, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+    npp = ctypes.POINTER(Normalize)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.kr_resize_bilinear.argtypes = [vp, i, i, i, i, vp, i, i, i, i, f, npp, vp]
+    L.kr_resize_bilinear.restype = i
+    L.kr_warp_affine.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
+    L.kr_warp_affine.restype = i
+    L.kr_invert_affine.argtypes = [dp, dp]
+    L.kr_invert_affine.restype = i
+    L.kr_status_string.argtypes = [i]
+    L.kr_status_string.restype = ctypes.c_char_p
+    L.kr_last_error.argtypes = []
+    L.kr_last_error.restype = ctypes.c_char_p
+    L.kr_hbm_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.kr_hbm_copy.restype = i
+    if hasattr(L, "kr_resize_batch"):
+        bip = ctypes.POINTER(BatchItem)
+        L.kr_resize_batch_workspace_size.argtypes = [i]
+        L.kr_resize_batch_workspace_size.restype = ctypes.c_size_t
+        L.kr_resize_batch.argtypes = [bip, i, i, i, i, i, f, npp, vp, ctypes.c_size_t, vp]
+        L.kr_resize_batch.restype = i
+        L.kr_batch_plan_create.argtypes = [bip, i, i, i, i, i, f, npp, ctypes.POINTER(vp)]
+        L.kr_batch_plan_create.restype = i
+        L.kr_batch_plan_launch.argtypes = [vp, vp]
+        L.kr_batch_plan_launch.restype = i
+        L.kr_batch_plan_destroy.argtypes = [vp]
+        L.kr_batch_plan_destroy.restype = None
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().kr_last_error().decode()
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise KrError(status, last_error())
+
+
+def _normalize(mean, std, c: int):
+    if mean is None:
+        return None
+    n = Normalize()
+    for k in range(c):
+        n.mean[k] = float(mean[k])
+        n.std[k] = float(std[k])
+    for k in range(c, 4):
+        n.std[k] = 1.0
+    return ctypes.pointer(n)
+
+
+def _m6(m):
+    vals = [float(v) for v in (m.reshape(-1).tolist() if hasattr(m, "reshape") else m)]
+    if len(vals) != 6:
+        raise ValueError("affine matrix needs 6 entries (row-major 2x3)")
+    return (ctypes.c_double * 6)(*vals)
+
+
+def _image(t):
+    """(pointer, H, W, C, kr_dtype) of a contiguous HWC (or HW) device tensor."""
+    import torch
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous HWC")
+    if t.dtype == torch.uint8:
+        dt = U8
+    elif t.dtype == torch.float32:
+        dt = F32
+    else:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    if t.dim() == 2:
+        h, w, c = t.shape[0], t.shape[1], 1
+    elif t.dim() == 3:
+        h, w, c = t.shape
+    else:
+        raise ValueError("tensor must be HxW or HxWxC")
+    return t.data_ptr(), int(h), int(w), int(c), dt
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def resize(src, dst, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
+           stream=None) -> None:
+    """kr_resize_bilinear on torch tensors: src HWC u8/f32 -> dst HWC (its size is the target)."""
+    sp, sh, sw, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if dc != c:
+        raise ValueError("src and dst channel counts differ")
+    check(lib().kr_resize_bilinear(sp, sh, sw, c, st, dp_, dh, dw, dt, border, float(border_value),
+                                   _normalize(mean, std, c), _stream(stream)))
+
+
+def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, border_value: float = 0.0,
+                mean=None, std=None, stream=None) -> None:
+    """kr_warp_affine on torch tensors; m is the row-major 2x3 map (source->destination
+    unless inverse)."""
+    sp, sh, sw, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if dc != c:
+        raise ValueError("src and dst channel counts differ")
+    check(lib().kr_warp_affine(sp, sh, sw, c, st, dp_, dh, dw, dt, _m6(m),
+                               WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
+                               _normalize(mean, std, c), _stream(stream)))
+
+
+def invert_affine(m):
+    """kr_invert_affine: the library's inverse of a 2x3 map (host computation)."""
+    out = (ctypes.c_double * 6)()
+    check(lib().kr_invert_affine(_m6(m), out))
+    return list(out)
+
+
+def hbm_copy(dst, src, nbytes: int | None = None, stream=None) -> None:
+    """kr_hbm_copy between two device tensors (the bandwidth ceiling probe)."""
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    check(lib().kr_hbm_copy(dst.data_ptr(), src.data_ptr(), n, _stream(stream)))

@@ -1,0 +1,141 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/kr.h declares, and rejects bad arguments synchronously (validation runs
+before any HIP call).  kr_invert_affine is host code and is compared bit for
+bit with the oracle's independent implementation of the same formula."""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_12425_amd import kr
+from paper_2505_12425_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kr.h")
+
+A = 0x7F0000000000  # a 16-byte aligned address; validation never dereferences it
+B = 0x7F0100000000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = kr.lib()
+    names = declared_functions()
+    assert "kr_resize_bilinear" in names and "kr_warp_affine" in names and "kr_resize_batch" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, f"declared in kr.h but not exported: {missing}"
+
+
+def resize(**kw):
+    a = dict(src=A, sh=480, sw=640, c=3, st=kr.U8, dst=B, dh=240, dw=320, dt=kr.U8,
+             border=kr.REPLICATE, bval=0.0, norm=None, stream=None)
+    a.update(kw)
+    return kr.lib().kr_resize_bilinear(a["src"], a["sh"], a["sw"], a["c"], a["st"], a["dst"], a["dh"],
+                                       a["dw"], a["dt"], a["border"], a["bval"], a["norm"], a["stream"])
+
+
+def warp(m=(1, 0, 0, 0, 1, 0), flags=0, **kw):
+    a = dict(src=A, sh=480, sw=640, c=3, st=kr.U8, dst=B, dh=480, dw=640, dt=kr.U8,
+             border=kr.CONSTANT, bval=0.0, norm=None, stream=None)
+    a.update(kw)
+    mm = (ctypes.c_double * 6)(*[float(v) for v in m])
+    return kr.lib().kr_warp_affine(a["src"], a["sh"], a["sw"], a["c"], a["st"], a["dst"], a["dh"],
+                                   a["dw"], a["dt"], mm, flags, a["border"], a["bval"], a["norm"],
+                                   a["stream"])
+
+
+def norm_ptr(std=(0.229, 0.224, 0.225)):
+    return kr._normalize((0.485, 0.456, 0.406), std, 3)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(src=0), kr.ERR_INVALID_ARGUMENT),
+    (dict(dst=0), kr.ERR_INVALID_ARGUMENT),
+    (dict(src=A + 4), kr.ERR_INVALID_ARGUMENT),
+    (dict(dst=B + 8), kr.ERR_INVALID_ARGUMENT),
+    (dict(sh=0), kr.ERR_INVALID_ARGUMENT),
+    (dict(dw=0), kr.ERR_INVALID_ARGUMENT),
+    (dict(sw=-3), kr.ERR_INVALID_ARGUMENT),
+    (dict(dh=32768), kr.ERR_INVALID_ARGUMENT),
+    (dict(c=0), kr.ERR_UNSUPPORTED),
+    (dict(c=5), kr.ERR_UNSUPPORTED),
+    (dict(st=kr.F32, dt=kr.U8), kr.ERR_UNSUPPORTED),
+    (dict(st=7), kr.ERR_UNSUPPORTED),
+    (dict(border=2), kr.ERR_UNSUPPORTED),
+    (dict(bval=256.0), kr.ERR_INVALID_ARGUMENT),
+    (dict(bval=-1.0), kr.ERR_INVALID_ARGUMENT),
+    (dict(bval=1.5), kr.ERR_INVALID_ARGUMENT),
+    (dict(bval=float("nan"), st=kr.F32, dt=kr.F32), kr.ERR_INVALID_ARGUMENT),
+    (dict(dst=A + 16 * 1000), kr.ERR_INVALID_ARGUMENT),  # overlaps src
+])
+def test_resize_rejects(kw, status):
+    assert resize(**kw) == status
+    assert kr.last_error() != ""
+
+
+def test_normalize_needs_f32_dst_and_nonzero_std():
+    assert resize(norm=norm_ptr()) == kr.ERR_INVALID_ARGUMENT
+    assert resize(dt=kr.F32, norm=norm_ptr(std=(0.2, 0.0, 0.2))) == kr.ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("m,flags,status", [
+    ((1, 2, 0, 2, 4, 0), 0, kr.ERR_SINGULAR_MATRIX),
+    ((0, 0, 0, 0, 0, 0), 0, kr.ERR_SINGULAR_MATRIX),
+    ((1, 0, float("nan"), 0, 1, 0), 0, kr.ERR_SINGULAR_MATRIX),
+    ((float("inf"), 0, 0, 0, 1, 0), kr.WARP_INVERSE_MAP, kr.ERR_SINGULAR_MATRIX),
+    ((1, 0, 0, 0, 1, 0), 4, kr.ERR_INVALID_ARGUMENT),
+])
+def test_warp_rejects(m, flags, status):
+    assert warp(m, flags) == status
+
+
+def test_warp_validates_images_too():
+    assert warp(src=A + 1) == kr.ERR_INVALID_ARGUMENT
+    assert warp(c=9) == kr.ERR_UNSUPPORTED
+
+
+def test_status_strings():
+    for s in range(7):
+        assert kr.lib().kr_status_string(s).decode()
+    assert kr.lib().kr_status_string(99).decode() == "unknown status"
+
+
+def test_invert_affine_matches_oracle_bitwise():
+    rng = np.random.default_rng(3)
+    for i in range(500):
+        if i % 2:
+            m = wl.affine_compose(2160, 3840, rng.uniform(-45, 45), rng.uniform(0.5, 1.5),
+                                  rng.uniform(-0.2, 0.2), rng.uniform(-400, 400), rng.uniform(-400, 400))
+        else:
+            m = rng.normal(size=(2, 3)) * 10.0 ** rng.integers(-3, 4)
+        got = kr.invert_affine(m.reshape(6))
+        exp = oracle.invert_affine(m.reshape(6))
+        assert got == list(exp), (m, got, exp)
+
+
+def test_invert_affine_rejects_singular():
+    with pytest.raises(kr.KrError) as e:
+        kr.invert_affine([2, 4, 1, 1, 2, 3])
+    assert e.value.status == kr.ERR_SINGULAR_MATRIX
+    # tiny but well-conditioned is fine (the rule is relative)
+    inv = kr.invert_affine([1e-9, 0, 0, 0, 1e-9, 0])
+    assert math.isclose(inv[0], 1e9)
+
+
+def test_copy_probe_validation():
+    L = kr.lib()
+    assert L.kr_hbm_copy(0, A, 16, None) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_hbm_copy(B, A + 3, 16, None) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_hbm_copy(A + 16, A, 64, None) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_hbm_copy(B, A, 0, None) == kr.OK  # nothing to do, nothing enqueued
