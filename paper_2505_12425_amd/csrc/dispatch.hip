@@ -1,15 +1,23 @@
-// dispatch.hip -- chooses the kernel for one image.
+// dispatch.hip -- chooses the kernel for one image: the LDS-tiled kernels for
+// u8 sources with 3 or 4 channels, the per-pixel kernels otherwise.
 #include "kr_device.h"
 
 namespace kr {
 
+bool tiled_supported(int c, kr_dtype st);
+hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
+
 hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
+    if (tiled_supported(c, st))
+        return launch_tiled(OP_RESIZE, c, dt, j, e, s);
     return launch_generic(OP_RESIZE, c, st, dt, j, e, s);
 }
 
 hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
+    if (tiled_supported(c, st))
+        return launch_tiled(OP_WARP, c, dt, j, e, s);
     return launch_generic(OP_WARP, c, st, dt, j, e, s);
 }
 

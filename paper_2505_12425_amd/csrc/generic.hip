@@ -23,55 +23,7 @@ __global__ __launch_bounds__(256) void k_generic(ImageJob j, Epilogue e)
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= j.dw || y >= j.dh)
         return;
-    int x0, y0, wx1, wy1;
-    float fx, fy;
-    if (OP == OP_RESIZE) {
-        resize_axis(x, j.sw, j.dw, x0, wx1, fx);
-        resize_axis(y, j.sh, j.dh, y0, wy1, fy);
-    } else {
-        const double xs = __builtin_fma(j.inv[0], (double)x, __builtin_fma(j.inv[1], (double)y, j.inv[2]));
-        const double ys = __builtin_fma(j.inv[3], (double)x, __builtin_fma(j.inv[4], (double)y, j.inv[5]));
-        warp_axis(xs, j.sw, x0, wx1, fx);
-        warp_axis(ys, j.sh, y0, wy1, fy);
-    }
-    const S *src = static_cast<const S *>(j.src);
-    D *dst = static_cast<D *>(j.dst) + ((size_t)y * (size_t)j.dw + (size_t)x) * C;
-    if constexpr (is_u8<D>::value) {
-        const int wx[2] = {2048 - wx1, wx1};
-        const int wy[2] = {2048 - wy1, wy1};
-        int acc[C];
-#pragma unroll
-        for (int c = 0; c < C; c++)
-            acc[c] = 0;
-#pragma unroll
-        for (int i = 0; i < 2; i++) {
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                const int w = wy[i] * wx[k];
-                int p[C];
-                tap_int<C>(src, j.sh, j.sw, x0 + k, y0 + i, e, p);
-#pragma unroll
-                for (int c = 0; c < C; c++)
-                    acc[c] += w * p[c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < C; c++)
-            dst[c] = (uint8_t)((acc[c] + (1 << 21)) >> 22);
-    } else {
-        float p00[C], p01[C], p10[C], p11[C];
-        tap_float<C>(src, j.sh, j.sw, x0, y0, e, p00);
-        tap_float<C>(src, j.sh, j.sw, x0 + 1, y0, e, p01);
-        tap_float<C>(src, j.sh, j.sw, x0, y0 + 1, e, p10);
-        tap_float<C>(src, j.sh, j.sw, x0 + 1, y0 + 1, e, p11);
-#pragma unroll
-        for (int c = 0; c < C; c++) {
-            const float top = (1.0f - fx) * p00[c] + fx * p01[c];
-            const float bot = (1.0f - fx) * p10[c] + fx * p11[c];
-            const float v = (1.0f - fy) * top + fy * bot;
-            dst[c] = v * e.alpha[c] + e.beta[c];
-        }
-    }
+    generic_pixel<C, S, D, OP>(j, e, x, y);
 }
 
 template <int C, typename S, typename D>

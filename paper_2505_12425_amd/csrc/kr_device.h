@@ -37,17 +37,31 @@ __device__ __forceinline__ int weight_from_ratio(int r, int den)
 }
 
 // Resize axis map with half-pixel centres: the source coordinate of output
-// index d is ((2 d + 1) n_in - n_out) / (2 n_out).  i0 = floor, w1 = 11-bit
-// weight of the upper tap, f = fraction as f32.  Sizes <= 32767 keep every
-// product within int32.
+// index d is ((2 d + 1) n_in - n_out) / (2 n_out), an exact rational.  i0 =
+// its floor, w1 = round-half-even(2048 * fraction), f = fraction as f32.
+//
+// Evaluated with correctly rounded binary64 divisions, which give the exact
+// integer results here.  When num / den is not an integer it lies at least
+// 1/den > 2^-16 below the next one, while |num / den| < 2^30 keeps the
+// rounding error under 2^-23: the floor is exact.  2048 r / den (< 2048) is
+// rounded once from exact integers: an exact half stays exact, and any other
+// value lies at least 1/(2 den) > 2^-17 from a half, far beyond the rounding
+// error, so rint (ties to even) rounds as the exact rational would.  Sizes
+// <= 32767 keep every product within int32.
+__device__ __forceinline__ int resize_i0(int d, int n_in, int n_out)
+{
+    const int num = (2 * d + 1) * n_in - n_out;
+    return (int)__builtin_floor((double)num / (double)(2 * n_out));
+}
+
 __device__ __forceinline__ void resize_axis(int d, int n_in, int n_out, int &i0, int &w1, float &f)
 {
     const int num = (2 * d + 1) * n_in - n_out;
     const int den = 2 * n_out;
-    const int q = floor_div(num, den);
+    const int q = (int)__builtin_floor((double)num / (double)den);
     const int r = num - q * den;
     i0 = q;
-    w1 = weight_from_ratio(r, den);
+    w1 = (int)__builtin_rint((double)(2048 * r) / (double)den);
     f = (float)r / (float)den;
 }
 
@@ -101,6 +115,62 @@ __device__ __forceinline__ void tap_float(const S *src, int h, int w, int x, int
 #pragma unroll
     for (int c = 0; c < C; c++)
         p[c] = (float)q[c];
+}
+
+// One output pixel (x, y) evaluated straight from the definition: every tap
+// read from global memory with its own border test.
+template <int C, typename S, typename D, int OP>
+__device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue &e, int x, int y)
+{
+    int x0, y0, wx1, wy1;
+    float fx, fy;
+    if (OP == OP_RESIZE) {
+        resize_axis(x, j.sw, j.dw, x0, wx1, fx);
+        resize_axis(y, j.sh, j.dh, y0, wy1, fy);
+    } else {
+        const double xs = __builtin_fma(j.inv[0], (double)x, __builtin_fma(j.inv[1], (double)y, j.inv[2]));
+        const double ys = __builtin_fma(j.inv[3], (double)x, __builtin_fma(j.inv[4], (double)y, j.inv[5]));
+        warp_axis(xs, j.sw, x0, wx1, fx);
+        warp_axis(ys, j.sh, y0, wy1, fy);
+    }
+    const S *src = static_cast<const S *>(j.src);
+    D *dst = static_cast<D *>(j.dst) + ((size_t)y * (size_t)j.dw + (size_t)x) * C;
+    if constexpr (is_u8<D>::value) {
+        const int wx[2] = {2048 - wx1, wx1};
+        const int wy[2] = {2048 - wy1, wy1};
+        int acc[C];
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            acc[c] = 0;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int w = wy[i] * wx[k];
+                int p[C];
+                tap_int<C>(src, j.sh, j.sw, x0 + k, y0 + i, e, p);
+#pragma unroll
+                for (int c = 0; c < C; c++)
+                    acc[c] += w * p[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            dst[c] = (uint8_t)((acc[c] + (1 << 21)) >> 22);
+    } else {
+        float p00[C], p01[C], p10[C], p11[C];
+        tap_float<C>(src, j.sh, j.sw, x0, y0, e, p00);
+        tap_float<C>(src, j.sh, j.sw, x0 + 1, y0, e, p01);
+        tap_float<C>(src, j.sh, j.sw, x0, y0 + 1, e, p10);
+        tap_float<C>(src, j.sh, j.sw, x0 + 1, y0 + 1, e, p11);
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            const float top = (1.0f - fx) * p00[c] + fx * p01[c];
+            const float bot = (1.0f - fx) * p10[c] + fx * p11[c];
+            const float v = (1.0f - fy) * top + fy * bot;
+            dst[c] = v * e.alpha[c] + e.beta[c];
+        }
+    }
 }
 
 }  // namespace kr

@@ -1,0 +1,915 @@
+// tiled.h -- LDS-tiled bilinear resize and affine warp for u8 sources with
+// 3 or 4 interleaved channels (device code shared by the per-image and the
+// batched kernels).
+//
+// One workgroup (4 waves) produces an output tile; each lane owns runs of PX
+// consecutive pixels (the lane layout is a template parameter, see Layout).
+//
+//  1. The source box the tile's 2x2 taps can touch is found from its corners
+//     (the inverse map is monotone along each output axis, so its extremes sit
+//     at the corners; resize uses exact per-column/per-row integer tables).
+//  2. The box rows are staged into LDS as one dword per pixel.  Staging walks
+//     16-pixel groups aligned on the image's linear pixel index: a group is 48
+//     (RGB) or 64 (RGBA) contiguous, 16-byte aligned bytes, read with dwordx4
+//     loads that a wave issues as contiguous 1 KB requests.  RGB groups are
+//     widened to one dword per pixel with byte-align ops.
+//  3. Each pixel reads its four taps with two ds_read2_b32, interpolates with
+//     v_perm (channel pairs) + v_dot2_u32_u16 (horizontal, 11-bit weights) +
+//     u24 multiply-adds (vertical).  Stores: with 4-pixel runs a lane writes
+//     12/16 contiguous bytes (u8) at once; with 1-pixel runs the 64 lanes of
+//     a wave own 64 consecutive pixels, so each store instruction writes one
+//     contiguous run (768 bytes of f32 RGB; RGB u8 packed across lane quads
+//     with one DPP exchange and a byte permute, 192 bytes).
+//
+// Border rule per tap.  Tiles whose box lies inside the image take no border
+// logic at all.  Other tiles stage clamped rows; REPLICATE additionally copies
+// edge pixels into the out-of-image columns of the box; CONSTANT zeroes the
+// weights of out-of-image taps and adds border * (missing weight).
+#pragma once
+
+#include "kr_device.h"
+
+namespace kr {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+constexpr int KT_THREADS = 256;
+constexpr int KT_MARGIN = 16;  // LDS dwords kept free on each side of a box row
+
+// Per-image parameters of the tiled kernels.
+struct TiledJob {
+    ImageJob j;
+    double m2048[6];  // warp inverse map scaled by 2048 (exact), for the u8 path
+    int op;           // OP_RESIZE or OP_WARP
+    int tiles_x;      // output tiles per row
+    int ntiles;       // output tiles in the image
+    int first_tile;   // index of the image's first tile in a batch work-list
+};
+
+// ------------------------------------------------------------------ helpers
+// round-half-even of a binary64 value |X| < 2^51 to int32: adding 1.5 * 2^52
+// leaves the rounded integer in the low mantissa bits.
+__device__ __forceinline__ int rne_i32(double X)
+{
+    const double r = X + 6755399441055744.0;
+    return (int)(uint32_t)__builtin_bit_cast(uint64_t, r);
+}
+
+__device__ __forceinline__ uint32_t udot2(uint32_t a, uint32_t b)
+{
+    return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), 0u, false);
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// k / d for 0 <= k < 2^22, 1 <= d < 2^22: a float-reciprocal estimate (off by
+// at most one) corrected with the exact remainder.
+__device__ __forceinline__ int udiv_small(int k, int d)
+{
+    int q = (int)((float)k * __builtin_amdgcn_rcpf((float)d));
+    const int r = k - q * d;
+    q += r >= d ? 1 : 0;
+    q -= r < 0 ? 1 : 0;
+    return q;
+}
+
+// Blocks are handed to the 8 XCDs round-robin; give each XCD one contiguous
+// run of tiles so that neighbouring tiles (which share source rows) meet in
+// the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int k = b & 7, q = n >> 3, r = n & 7;
+    return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+// One source pixel of C <= 4 u8 channels as a dword (byte c = channel c),
+// read byte by byte (used off the fast path).
+template <int C>
+__device__ __forceinline__ uint32_t load_px_bytes(const uint8_t *src, size_t lin)
+{
+    const uint8_t *p = src + lin * C;
+    uint32_t v = 0;
+#pragma unroll
+    for (int c = 0; c < C; c++)
+        v |= (uint32_t)p[c] << (8 * c);
+    return v;
+}
+
+// ------------------------------------------------------------------ pixel math
+// u8 interpolation of one pixel from its four tap dwords (byte c = channel c).
+// wxp packs the horizontal weights w0 | w1 << 16 (w0 + w1 = 2048); wy0_4,
+// wy1_4 are 4x the vertical weights.  Per channel and tap row, v_perm builds
+// the u16 pair (left, right) and v_dot2 forms h = w0 l + w1 r (< 2^20) plus
+// 1024; then v = wy0_4 h0 + wy1_4 h1 = 4 acc + 1024 (wy0_4 + wy1_4), which is
+// 4 acc + 2^23 when the vertical weights sum to 2048.  Channel c's output is
+// the top byte of v[c]: (4 acc + 2^23) >> 24 == (acc + 2^21) >> 22.
+template <int C>
+__device__ __forceinline__ void interp_u8(uint32_t t00, uint32_t t01, uint32_t t10, uint32_t t11, uint32_t wxp,
+                                          uint32_t wy0_4, uint32_t wy1_4, uint32_t (&v)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const uint32_t sel = (uint32_t)c | 0x00000C00u | ((uint32_t)(4 + c) << 16) | 0x0C000000u;
+        const uint32_t h0 = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, __builtin_amdgcn_perm(t01, t00, sel)),
+                                                   __builtin_bit_cast(u16x2, wxp), 1024u, false);
+        const uint32_t h1 = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, __builtin_amdgcn_perm(t11, t10, sel)),
+                                                   __builtin_bit_cast(u16x2, wxp), 1024u, false);
+        v[c] = __umul24(h1, wy1_4) + __umul24(h0, wy0_4);
+    }
+}
+
+// CONSTANT border on an edge tile: zero the weights of out-of-image taps
+// (tap (i, j) is inside iff row i and column j are) and return what must be
+// added to v so that it equals 4 (acc + border * missing weight) + 2^23.
+__device__ __forceinline__ uint32_t mask_weights(int x0, int y0, int W, int H, uint32_t &wx0, uint32_t &wx1,
+                                                 uint32_t &wy0, uint32_t &wy1, uint32_t bval)
+{
+    wx0 = (unsigned)x0 < (unsigned)W ? wx0 : 0u;
+    wx1 = (unsigned)(x0 + 1) < (unsigned)W ? wx1 : 0u;
+    wy0 = (unsigned)y0 < (unsigned)H ? wy0 : 0u;
+    wy1 = (unsigned)(y0 + 1) < (unsigned)H ? wy1 : 0u;
+    const uint32_t missing = (1u << 22) - __umul24(wy0 + wy1, wx0 + wx1);
+    return (1u << 23) - 4096u * (wy0 + wy1) + 4u * bval * missing;
+}
+
+// f32 interpolation with unquantised weights, then out = v * alpha + beta.
+template <int C>
+__device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t t10, uint32_t t11, float wx0,
+                                           float wx1, float wy0, float wy1, float extra, const Epilogue &e,
+                                           float (&o)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const float p00 = (float)((t00 >> (8 * c)) & 0xFFu);
+        const float p01 = (float)((t01 >> (8 * c)) & 0xFFu);
+        const float p10 = (float)((t10 >> (8 * c)) & 0xFFu);
+        const float p11 = (float)((t11 >> (8 * c)) & 0xFFu);
+        const float top = wx0 * p00 + wx1 * p01;
+        const float bot = wx0 * p10 + wx1 * p11;
+        const float v = wy0 * top + wy1 * bot + extra;
+        o[c] = v * e.alpha[c] + e.beta[c];
+    }
+}
+
+// ------------------------------------------------------------------ stores
+// Lane layout (see compute below): a lane owns PX consecutive pixels of a row.
+// PX = 4: the lane stores 4 pixels at once (12/16 contiguous bytes for u8,
+// 48/64 for f32).  PX = 1: the 64 lanes of a wave own 64 consecutive pixels of
+// one row, so each store instruction writes one contiguous run (RGB u8 is
+// packed across lane quads with a DPP exchange).
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Pack per-channel results (top byte of v[c]) into one pixel dword, byte c =
+// channel c.
+template <int C>
+__device__ __forceinline__ uint32_t pack_px(const uint32_t (&v)[C])
+{
+    if constexpr (C == 3)
+        return __builtin_amdgcn_perm(v[2], __builtin_amdgcn_perm(v[1], v[0], 0x0C0C0703u), 0x0C070100u);
+    else
+        return __builtin_amdgcn_perm(v[3], v[2], 0x07030C0Cu) | __builtin_amdgcn_perm(v[1], v[0], 0x0C0C0703u);
+}
+
+// Whether 4-pixel chunks starting at multiple-of-4 columns of rows dw pixels
+// wide are aligned for the vector stores below (RGB u8: 4 bytes; otherwise
+// 16); the destination base is 16-byte aligned.
+template <int C, bool F32>
+__device__ __forceinline__ bool store4_aligned(int dw)
+{
+    const size_t row_bytes = (size_t)dw * C * (F32 ? 4 : 1);
+    return (row_bytes & ((C == 3 && !F32) ? 3 : 15)) == 0;
+}
+
+// Four u8 pixels (pixel k = P[k], byte c = channel c); n valid pixels.
+template <int C>
+__device__ __forceinline__ void store_u8_4(uint8_t *p, int n, bool aligned, const uint32_t (&P)[4])
+{
+    if (n == 4 && aligned) {
+        if constexpr (C == 3) {
+            struct __attribute__((packed, aligned(4))) W3 { uint32_t a, b, c; };
+            // R0 G0 B0 R1 | G1 B1 R2 G2 | B2 R3 G3 B3
+            *reinterpret_cast<W3 *>(p) = W3{__builtin_amdgcn_perm(P[1], P[0], 0x04020100u),
+                                            __builtin_amdgcn_perm(P[2], P[1], 0x05040201u),
+                                            __builtin_amdgcn_perm(P[3], P[2], 0x06050402u)};
+        } else {
+            *reinterpret_cast<u32x4 *>(p) = u32x4{P[0], P[1], P[2], P[3]};
+        }
+    } else {
+        for (int k = 0; k < n; k++)
+#pragma unroll
+            for (int c = 0; c < C; c++)
+                p[k * C + c] = (uint8_t)(P[k] >> (8 * c));
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void store_f32_4(float *p, int n, bool aligned, const float (&o)[4][C])
+{
+    if (n == 4 && aligned) {
+        f32x4 *q = reinterpret_cast<f32x4 *>(p);
+        if constexpr (C == 3) {
+            q[0] = f32x4{o[0][0], o[0][1], o[0][2], o[1][0]};
+            q[1] = f32x4{o[1][1], o[1][2], o[2][0], o[2][1]};
+            q[2] = f32x4{o[2][2], o[3][0], o[3][1], o[3][2]};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                q[k] = f32x4{o[k][0], o[k][1], o[k][2], o[k][3]};
+        }
+    } else {
+        for (int k = 0; k < n; k++)
+#pragma unroll
+            for (int c = 0; c < C; c++)
+                p[k * C + c] = o[k][c];
+    }
+}
+
+// Byte selectors of the three dwords a quad of RGB pixels packs into: lane j
+// of the quad takes bytes [j, j + 4) of {own 0, own 1, own 2, next 0, next 1,
+// next 2}.
+__device__ __forceinline__ uint32_t quad_selector(int j)
+{
+    return (uint32_t)(0x0000060504020100ull >> (8 * j));
+}
+
+// One u8 pixel per lane (PX = 1).  RGB: all lanes of the wave must call this
+// together (the quad exchange reads the neighbouring lane); quads inside the
+// row store three packed dwords, a ragged tail quad stores bytes.
+template <int C>
+__device__ __forceinline__ void store_u8_px(uint8_t *row, int x, int x_end, bool row_aligned, uint32_t P, uint32_t sel)
+{
+    if constexpr (C == 4) {
+        if (x < x_end)
+            *reinterpret_cast<uint32_t *>(row + 4 * (size_t)x) = P;
+    } else {
+        const uint32_t Pn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)P, 0xF9, 0xF, 0xF, false);
+        const int j = lane_id() & 3;
+        const int xq = x - j;
+        if (row_aligned && xq + 3 < x_end) {
+            if (j < 3)
+                *reinterpret_cast<uint32_t *>(row + 3 * (size_t)xq + 4 * j) = __builtin_amdgcn_perm(Pn, P, sel);
+        } else if (x < x_end) {
+            uint8_t *q = row + 3 * (size_t)x;
+            q[0] = (uint8_t)P;
+            q[1] = (uint8_t)(P >> 8);
+            q[2] = (uint8_t)(P >> 16);
+        }
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void store_f32_px(float *row, int x, int x_end, const float (&o)[C])
+{
+    if (x >= x_end)
+        return;
+    if constexpr (C == 3) {
+        struct __attribute__((packed, aligned(4))) F3 { float a, b, c; };
+        *reinterpret_cast<F3 *>(row + 3 * (size_t)x) = F3{o[0], o[1], o[2]};
+    } else {
+        *reinterpret_cast<f32x4 *>(row + 4 * (size_t)x) = f32x4{o[0], o[1], o[2], o[3]};
+    }
+}
+
+// Store the PX pixels of one lane run starting at column x (u8).
+template <int C, int PX>
+__device__ __forceinline__ void store_run_u8(uint8_t *row, int x, int x_end, bool aligned, const uint32_t (&P)[PX],
+                                             uint32_t sel)
+{
+    if constexpr (PX == 4)
+        store_u8_4<C>(row + (size_t)x * C, min(4, x_end - x), aligned, P);
+    else
+        store_u8_px<C>(row, x, x_end, aligned, P[0], sel);
+}
+
+template <int C, int PX>
+__device__ __forceinline__ void store_run_f32(float *row, int x, int x_end, bool aligned, const float (&o)[PX][C])
+{
+    if constexpr (PX == 4) {
+        if (x < x_end)
+            store_f32_4<C>(row + (size_t)x * C, min(4, x_end - x), aligned, o);
+    } else {
+        store_f32_px<C>(row, x, x_end, o[0]);
+    }
+}
+
+// ------------------------------------------------------------------ tile plan
+// Launch-wide LDS geometry: every tile of a launch stages into rows x pitch dwords.
+struct TileGeom {
+    int pitch;  // LDS row pitch in dwords (>= box width + 2 * KT_MARGIN)
+    int rows;   // LDS rows (box rows for warps, 2 * tile height for resizes)
+};
+
+// Everything one tile needs, uniform across the workgroup.
+struct Plan {
+    int ox0, oy0, ox1, oy1;  // output pixels covered (inclusive)
+    int bx0, bw;             // box columns [bx0, bx0 + bw)
+    int by0, nslots;         // warp: slot s = source row by0 + s; resize: two slots per output row
+    int cx0, cx1, ng;        // in-image box columns; 16-pixel groups per slot (upper bound)
+    bool inside;             // every tap of the tile lies inside the image
+    bool direct;             // box exceeds the LDS budget: per-pixel evaluation
+};
+
+// u8 coordinate of one axis: the 2048-scaled binary64 coordinate X gives
+// N = rne(X), x0 = N >> 11, w1 = N & 2047.  This equals floor and
+// round-half-even of the unscaled coordinate: rne(2048 xs) = 2048 floor(xs) +
+// rne(2048 frac); when rne(2048 frac) = 2048 the taps move right by one with
+// weights (2048, 0), which gives the same exact sum.  Scaling by 2048 is exact,
+// so fma(2048 A, x, fma(2048 B, y, 2048 C)) = 2048 fma(A, x, fma(B, y, C)).
+__device__ __forceinline__ double clamp_scaled(double X, int n)
+{
+    const double lo = -4096.0, hi = 2048.0 * ((double)n + 1.0);
+    return X < lo ? lo : (X > hi ? hi : X);
+}
+
+__device__ __forceinline__ double clamp_plain(double X, int n)
+{
+    const double hi = (double)n + 1.0;
+    return X < -2.0 ? -2.0 : (X > hi ? hi : X);
+}
+
+template <int OP, int TW, int TH, bool F32>
+__device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const TileGeom &G)
+{
+    const ImageJob &j = t.j;
+    const int H = j.sh, W = j.sw;
+    Plan p;
+    const int ty = tile / t.tiles_x, tx = tile - ty * t.tiles_x;
+    p.ox0 = tx * TW;
+    p.oy0 = ty * TH;
+    p.ox1 = min(p.ox0 + TW, j.dw) - 1;
+    p.oy1 = min(p.oy0 + TH, j.dh) - 1;
+    int x0min, x0max, y0min, y0max;
+    if constexpr (OP == OP_RESIZE) {
+        x0min = resize_i0(p.ox0, W, j.dw);
+        x0max = resize_i0(p.ox1, W, j.dw);
+        y0min = resize_i0(p.oy0, H, j.dh);
+        y0max = resize_i0(p.oy1, H, j.dh);
+        p.inside = x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
+        p.by0 = 0;
+        p.nslots = 2 * (p.oy1 - p.oy0 + 1);
+    } else {
+        // Tap box from the four corners.  fma(A, x, fma(B, y, C)) is monotone in
+        // x and in y separately, and so are the clamp and the rounding, so the
+        // extremes over the tile sit at its corners.  First unclamped, to find
+        // interior tiles (no clamp, no border logic per pixel).
+        const double *m = F32 ? j.inv : t.m2048;
+        const double b = F32 ? 1.0e9 : 2.0e9;  // keeps the integer conversion in range
+        x0min = y0min = 0x7fffffff;
+        x0max = y0max = -0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const double cx = (double)((q & 1) ? p.ox1 : p.ox0), cy = (double)((q & 2) ? p.oy1 : p.oy0);
+            double X = __builtin_fma(m[0], cx, __builtin_fma(m[1], cy, m[2]));
+            double Y = __builtin_fma(m[3], cx, __builtin_fma(m[4], cy, m[5]));
+            X = X < -b ? -b : (X > b ? b : X);
+            Y = Y < -b ? -b : (Y > b ? b : Y);
+            const int ix = F32 ? (int)__builtin_floor(X) : (rne_i32(X) >> 11);
+            const int iy = F32 ? (int)__builtin_floor(Y) : (rne_i32(Y) >> 11);
+            x0min = min(x0min, ix); x0max = max(x0max, ix);
+            y0min = min(y0min, iy); y0max = max(y0max, iy);
+        }
+        p.inside = x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
+        if (!p.inside) {
+            x0min = y0min = 0x7fffffff;
+            x0max = y0max = -0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const double cx = (double)((q & 1) ? p.ox1 : p.ox0), cy = (double)((q & 2) ? p.oy1 : p.oy0);
+                const double X = __builtin_fma(m[0], cx, __builtin_fma(m[1], cy, m[2]));
+                const double Y = __builtin_fma(m[3], cx, __builtin_fma(m[4], cy, m[5]));
+                int ix, iy;
+                if (F32) {
+                    ix = (int)__builtin_floor(clamp_plain(X, W));
+                    iy = (int)__builtin_floor(clamp_plain(Y, H));
+                } else {
+                    ix = rne_i32(clamp_scaled(X, W)) >> 11;
+                    iy = rne_i32(clamp_scaled(Y, H)) >> 11;
+                }
+                x0min = min(x0min, ix); x0max = max(x0max, ix);
+                y0min = min(y0min, iy); y0max = max(y0max, iy);
+            }
+        }
+        p.by0 = y0min;
+        p.nslots = y0max + 2 - y0min;
+    }
+    p.bx0 = x0min;
+    p.bw = x0max + 2 - x0min;
+    p.direct = p.bw + 2 * KT_MARGIN > G.pitch || p.nslots > G.rows;
+    p.cx0 = max(p.bx0, 0);
+    p.cx1 = min(p.bx0 + p.bw - 1, W - 1);
+    p.ng = (p.direct || p.cx0 > p.cx1) ? 0 : ((p.cx1 - p.cx0) >> 4) + 2;
+    return p;
+}
+
+// Source row held by LDS slot s (inside [0, H - 1]).
+template <int OP>
+__device__ __forceinline__ int slot_row(const TiledJob &t, const Plan &p, int s)
+{
+    const ImageJob &j = t.j;
+    int y;
+    if constexpr (OP == OP_RESIZE) {
+        y = resize_i0(p.oy0 + (s >> 1), j.sh, j.dh) + (s & 1);
+    } else {
+        y = p.by0 + s;
+    }
+    return clampi(y, 0, j.sh - 1);
+}
+
+// ------------------------------------------------------------------ staging
+// Box rows are staged as one dword per pixel.  Work item k covers one
+// 16-pixel group (aligned on the image's linear pixel index) of one slot:
+// 48 (RGB) or 64 (RGBA) contiguous, 16-byte aligned source bytes.
+template <int C> struct GroupRegs { u32x4 q[C == 3 ? 3 : 4]; };
+
+template <int C, int MAXIT> struct Prefetch {
+    GroupRegs<C> g[MAXIT];
+    int dst[MAXIT];  // LDS dword index of the group's first pixel, -1 = none
+    int p0[MAXIT];   // linear index of the group's first pixel
+};
+
+// Locate work item k: its LDS destination and first pixel, or false.
+template <int OP>
+__device__ __forceinline__ bool group_of(const TiledJob &t, const Plan &p, const TileGeom &G, int k, int &dst, int &p0)
+{
+    // slot-major: consecutive lanes take the same group index of consecutive
+    // slots, so with a pitch of 17 (mod 32) their 16-dword writes start on
+    // different LDS banks
+    const int gi = udiv_small(k, p.nslots);
+    const int s = k - gi * p.nslots;
+    const int rowbase = slot_row<OP>(t, p, s) * t.j.sw;
+    const int g = ((rowbase + p.cx0) >> 4) + gi;
+    if (g > ((rowbase + p.cx1) >> 4))
+        return false;
+    p0 = g << 4;
+    dst = s * G.pitch + KT_MARGIN + (p0 - rowbase - p.bx0);
+    return true;
+}
+
+template <int C>
+__device__ __forceinline__ void load_group(const uint8_t *__restrict__ src, int p0, GroupRegs<C> &r)
+{
+    const u32x4 *q = reinterpret_cast<const u32x4 *>(src + (size_t)p0 * C);
+#pragma unroll
+    for (int i = 0; i < (C == 3 ? 3 : 4); i++)
+        r.q[i] = q[i];
+}
+
+// Widen a loaded group to 16 pixel dwords in LDS (RGB: byte 3 is unspecified).
+template <int C>
+__device__ __forceinline__ void write_group(uint32_t *d, const GroupRegs<C> &r)
+{
+    if constexpr (C == 3) {
+        const uint32_t w[12] = {r.q[0].x, r.q[0].y, r.q[0].z, r.q[0].w, r.q[1].x, r.q[1].y,
+                                r.q[1].z, r.q[1].w, r.q[2].x, r.q[2].y, r.q[2].z, r.q[2].w};
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const uint32_t u0 = w[3 * t], u1 = w[3 * t + 1], u2 = w[3 * t + 2];
+            d[4 * t + 0] = u0;
+            d[4 * t + 1] = __builtin_amdgcn_alignbyte(u1, u0, 3);
+            d[4 * t + 2] = __builtin_amdgcn_alignbyte(u2, u1, 2);
+            d[4 * t + 3] = u2 >> 8;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            d[4 * t + 0] = r.q[t].x;
+            d[4 * t + 1] = r.q[t].y;
+            d[4 * t + 2] = r.q[t].z;
+            d[4 * t + 3] = r.q[t].w;
+        }
+    }
+}
+
+// The image's last group may end past the buffer: read it pixel by pixel.
+template <int C>
+__device__ __noinline__ void write_tail_group(uint32_t *d, const uint8_t *src, int p0, int hw)
+{
+#pragma unroll 1
+    for (int i = 0; i < 16 && p0 + i < hw; i++)
+        d[i] = load_px_bytes<C>(src, (size_t)(p0 + i));
+}
+
+// Issue the loads of this thread's first MAXIT work items of a tile.
+template <int OP, int C, int MAXIT>
+__device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const TileGeom &G, Prefetch<C, MAXIT> &pf)
+{
+    const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
+    const int hw = t.j.sh * t.j.sw;
+    const int total = p.nslots * p.ng;
+#pragma unroll
+    for (int it = 0; it < MAXIT; it++) {
+        const int k = threadIdx.x + it * KT_THREADS;
+        pf.dst[it] = -1;
+        int dst, p0;
+        if (k < total && group_of<OP>(t, p, G, k, dst, p0)) {
+            pf.dst[it] = dst;
+            pf.p0[it] = p0;
+            if (p0 + 16 <= hw)
+                load_group<C>(src, p0, pf.g[it]);
+        }
+    }
+}
+
+// Write the prefetched groups to LDS, then stage any remaining work items
+// directly (boxes larger than MAXIT groups per thread).
+template <int OP, int C, int MAXIT>
+__device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const TileGeom &G,
+                                       const Prefetch<C, MAXIT> &pf, uint32_t *lds)
+{
+    const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
+    const int hw = t.j.sh * t.j.sw;
+#pragma unroll
+    for (int it = 0; it < MAXIT; it++) {
+        if (pf.dst[it] >= 0) {
+            if (pf.p0[it] + 16 <= hw)
+                write_group<C>(lds + pf.dst[it], pf.g[it]);
+            else
+                write_tail_group<C>(lds + pf.dst[it], src, pf.p0[it], hw);
+        }
+    }
+    const int total = p.nslots * p.ng;
+    for (int k = threadIdx.x + MAXIT * KT_THREADS; k < total; k += KT_THREADS) {
+        int dst, p0;
+        if (!group_of<OP>(t, p, G, k, dst, p0))
+            continue;
+        if (p0 + 16 <= hw) {
+            GroupRegs<C> r;
+            load_group<C>(src, p0, r);
+            write_group<C>(lds + dst, r);
+        } else {
+            write_tail_group<C>(lds + dst, src, p0, hw);
+        }
+    }
+}
+
+// REPLICATE on a box that crosses the left/right image edge: the out-of-image
+// columns of each slot take the slot row's edge pixel (read from global memory).
+__device__ __forceinline__ bool needs_edge_fill(const TiledJob &t, const Plan &p, const Epilogue &e)
+{
+    return !p.direct && !p.inside && e.border == KR_BORDER_REPLICATE &&
+           (p.bx0 < 0 || p.bx0 + p.bw - 1 > t.j.sw - 1);
+}
+
+template <int OP, int C>
+__device__ __forceinline__ void fill_edge_columns(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds)
+{
+    const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
+    const int W = t.j.sw;
+    const int nl = p.bx0 < 0 ? -p.bx0 : 0;
+    const int last = p.bx0 + p.bw - 1;
+    const int nr = last > W - 1 ? last - (W - 1) : 0;
+    const int per = nl + nr;
+    for (int k = threadIdx.x; k < p.nslots * per; k += KT_THREADS) {
+        const int s = udiv_small(k, per);
+        const int jj = k - s * per;
+        const int col = jj < nl ? jj : p.bw - nr + (jj - nl);
+        const int xc = clampi(p.bx0 + col, 0, W - 1);
+        lds[s * G.pitch + KT_MARGIN + col] = load_px_bytes<C>(src, (size_t)slot_row<OP>(t, p, s) * W + xc);
+    }
+}
+
+// Resize tables after the box: per column (x0 - bx0 + margin, weights) and per
+// output row (y0, weight).  F32: weights are the fraction's bit pattern.
+template <int TW, int TH, bool F32>
+__device__ __forceinline__ void resize_tables(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds)
+{
+    const ImageJob &j = t.j;
+    uint32_t *tab = lds + G.rows * G.pitch;
+    for (int i = threadIdx.x; i < TW + TH; i += KT_THREADS) {
+        int i0, w1;
+        float f;
+        if (i < TW) {
+            resize_axis(min(p.ox0 + i, p.ox1), j.sw, j.dw, i0, w1, f);
+            tab[i] = (uint32_t)(i0 - p.bx0 + KT_MARGIN);
+            tab[TW + i] = F32 ? __builtin_bit_cast(uint32_t, f) : ((uint32_t)(2048 - w1) | ((uint32_t)w1 << 16));
+        } else {
+            resize_axis(min(p.oy0 + (i - TW), p.oy1), j.sh, j.dh, i0, w1, f);
+            tab[2 * TW + (i - TW)] = (uint32_t)i0;
+            tab[2 * TW + TH + (i - TW)] = F32 ? __builtin_bit_cast(uint32_t, f) : (uint32_t)w1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ compute
+// Lane layout: TXT lanes per tile row (64 / TXT rows per wave), each owning a
+// run of PX consecutive pixels; CPT runs per lane, TXT * PX apart; RPT rows
+// per lane, 256 / TXT apart.  Tile = (TXT * PX * CPT) x ((256 / TXT) * RPT).
+// Pixels past the tile's right edge are computed as its last column (PX = 1
+// keeps every lane in the quad exchange) and not stored.
+template <int PX_, int TXT_, int CPT_, int RPT_> struct Layout {
+    static_assert(PX_ == 4 || (PX_ == 1 && TXT_ == 64), "one-pixel runs need whole-wave rows");
+    static constexpr int PX = PX_, TXT = TXT_, CPT = CPT_, RPT = RPT_;
+    static constexpr int SEG = TXT * PX;             // columns between a lane's runs
+    static constexpr int TW = SEG * CPT;
+    static constexpr int ROWS = KT_THREADS / TXT;    // tile rows per pass
+    static constexpr int TH = ROWS * RPT;
+    __device__ static int col0() { return PX * (int)(threadIdx.x % TXT); }
+    __device__ static int row0() { return (int)(threadIdx.x / TXT); }
+};
+
+template <int C, bool F32, class L>
+__device__ __forceinline__ bool layout_aligned(int dw)
+{
+    if constexpr (L::PX == 4)
+        return store4_aligned<C, F32>(dw);
+    else
+        return F32 || C == 4 || (((size_t)dw * C) & 3) == 0;
+}
+
+template <int OP, int C, bool F32, class L>
+__device__ __forceinline__ void compute_direct(const TiledJob &t, const Plan &p, const Epilogue &e)
+{
+    for (int r = 0; r < L::RPT; r++) {
+        const int y = p.oy0 + L::row0() + r * L::ROWS;
+        if (y > p.oy1)
+            break;
+        for (int c = 0; c < L::CPT; c++) {
+            for (int k = 0; k < L::PX; k++) {
+                const int x = p.ox0 + c * L::SEG + L::col0() + k;
+                if (x > p.ox1)
+                    continue;
+                if constexpr (F32)
+                    generic_pixel<C, uint8_t, float, OP>(t.j, e, x, y);
+                else
+                    generic_pixel<C, uint8_t, uint8_t, OP>(t.j, e, x, y);
+            }
+        }
+    }
+}
+
+template <int C, bool F32, class L, bool CLAMP, bool MASK>
+__device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
+                                               const uint32_t *lds)
+{
+    constexpr int PX = L::PX, CPT = L::CPT;
+    const ImageJob &j = t.j;
+    const int W = j.sw, H = j.sh;
+    double m[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+        m[i] = F32 ? j.inv[i] : t.m2048[i];
+    const int pitch = G.pitch;
+    const int base = p.by0 * pitch + p.bx0 - KT_MARGIN;
+    const bool aligned = layout_aligned<C, F32, L>(j.dw);
+    const uint32_t sel = quad_selector(lane_id() & 3);
+    const int x_end = p.ox1 + 1;
+    double xd[CPT][PX];
+#pragma unroll
+    for (int c = 0; c < CPT; c++)
+#pragma unroll
+        for (int k = 0; k < PX; k++)
+            xd[c][k] = (double)min(p.ox0 + c * L::SEG + L::col0() + k, p.ox1);
+    for (int r = 0; r < L::RPT; r++) {
+        const int y = p.oy0 + L::row0() + r * L::ROWS;
+        if (y > p.oy1)
+            break;
+        const double rowX = __builtin_fma(m[1], (double)y, m[2]);
+        const double rowY = __builtin_fma(m[4], (double)y, m[5]);
+        const size_t row_off = (size_t)y * (size_t)j.dw * C;
+#pragma unroll
+        for (int c = 0; c < CPT; c++) {
+            const int xr = p.ox0 + c * L::SEG + L::col0();
+            if constexpr (!F32) {
+                uint32_t P[PX];
+#pragma unroll
+                for (int k = 0; k < PX; k++) {
+                    double X = __builtin_fma(m[0], xd[c][k], rowX);
+                    double Y = __builtin_fma(m[3], xd[c][k], rowY);
+                    if (CLAMP) {
+                        X = clamp_scaled(X, W);
+                        Y = clamp_scaled(Y, H);
+                    }
+                    const int Nx = rne_i32(X), Ny = rne_i32(Y);
+                    const int x0 = Nx >> 11, y0 = Ny >> 11;
+                    uint32_t wx1 = (uint32_t)Nx & 2047u, wy1 = (uint32_t)Ny & 2047u;
+                    uint32_t wx0 = 2048u - wx1, wy0 = 2048u - wy1;
+                    uint32_t corr = 0;
+                    if (MASK)
+                        corr = mask_weights(x0, y0, W, H, wx0, wx1, wy0, wy1, (uint32_t)e.bval_i);
+                    const int a = __mul24(y0, pitch) + x0 - base;
+                    uint32_t v[C];
+                    interp_u8<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0 | (wx1 << 16), wy0 << 2,
+                                 wy1 << 2, v);
+                    if (MASK) {
+#pragma unroll
+                        for (int q = 0; q < C; q++)
+                            v[q] += corr;
+                    }
+                    P[k] = pack_px<C>(v);
+                }
+                store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + row_off, xr, x_end, aligned, P, sel);
+            } else {
+                float o[PX][C];
+#pragma unroll
+                for (int k = 0; k < PX; k++) {
+                    double X = __builtin_fma(m[0], xd[c][k], rowX);
+                    double Y = __builtin_fma(m[3], xd[c][k], rowY);
+                    if (CLAMP) {
+                        X = clamp_plain(X, W);
+                        Y = clamp_plain(Y, H);
+                    }
+                    const double fxl = __builtin_floor(X), fyl = __builtin_floor(Y);
+                    const int x0 = (int)fxl, y0 = (int)fyl;
+                    const float fx = (float)(X - fxl), fy = (float)(Y - fyl);
+                    float wx0 = 1.0f - fx, wx1 = fx, wy0 = 1.0f - fy, wy1 = fy, extra = 0.0f;
+                    if (MASK) {
+                        wx0 = (unsigned)x0 < (unsigned)W ? wx0 : 0.0f;
+                        wx1 = (unsigned)(x0 + 1) < (unsigned)W ? wx1 : 0.0f;
+                        wy0 = (unsigned)y0 < (unsigned)H ? wy0 : 0.0f;
+                        wy1 = (unsigned)(y0 + 1) < (unsigned)H ? wy1 : 0.0f;
+                        extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
+                    }
+                    const int a = __mul24(y0, pitch) + x0 - base;
+                    interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
+                                  e, o[k]);
+                }
+                store_run_f32<C, PX>(static_cast<float *>(j.dst) + row_off, xr, x_end, aligned, o);
+            }
+        }
+    }
+}
+
+template <int C, bool F32, class L>
+__device__ __forceinline__ void compute_warp(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
+                                             const uint32_t *lds)
+{
+    if (p.inside)
+        compute_warp_t<C, F32, L, false, false>(t, p, G, e, lds);
+    else if (e.border == KR_BORDER_CONSTANT)
+        compute_warp_t<C, F32, L, true, true>(t, p, G, e, lds);
+    else
+        compute_warp_t<C, F32, L, true, false>(t, p, G, e, lds);
+}
+
+template <int C, bool F32, class L, bool MASK>
+__device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
+                                                 const uint32_t *lds)
+{
+    constexpr int PX = L::PX, CPT = L::CPT, TW = L::TW, TH = L::TH;
+    const ImageJob &j = t.j;
+    const int H = j.sh, W = j.sw;
+    const uint32_t *tab = lds + G.rows * G.pitch;
+    const int pitch = G.pitch;
+    const bool aligned = layout_aligned<C, F32, L>(j.dw);
+    const uint32_t sel = quad_selector(lane_id() & 3);
+    const int x_end = p.ox1 + 1;
+    int ca[CPT][PX];
+    uint32_t cw[CPT][PX];
+#pragma unroll
+    for (int c = 0; c < CPT; c++)
+#pragma unroll
+        for (int k = 0; k < PX; k++) {
+            const int cc = min(c * L::SEG + L::col0() + k, p.ox1 - p.ox0);
+            ca[c][k] = (int)tab[cc];
+            cw[c][k] = tab[TW + cc];
+        }
+    for (int r = 0; r < L::RPT; r++) {
+        const int rr = L::row0() + r * L::ROWS;
+        const int y = p.oy0 + rr;
+        if (y > p.oy1)
+            break;
+        const int y0 = (int)tab[2 * TW + rr];
+        const uint32_t rw = tab[2 * TW + TH + rr];
+        const int s0 = (2 * rr) * pitch;
+        const size_t row_off = (size_t)y * (size_t)j.dw * C;
+        const bool vy0 = (unsigned)y0 < (unsigned)H, vy1 = (unsigned)(y0 + 1) < (unsigned)H;
+#pragma unroll
+        for (int c = 0; c < CPT; c++) {
+            const int xr = p.ox0 + c * L::SEG + L::col0();
+            if constexpr (!F32) {
+                uint32_t P[PX];
+#pragma unroll
+                for (int k = 0; k < PX; k++) {
+                    const int a = s0 + ca[c][k];
+                    uint32_t wy1 = rw, wy0 = 2048u - rw;
+                    uint32_t wx0 = cw[c][k] & 0xFFFFu, wx1 = cw[c][k] >> 16, corr = 0;
+                    if (MASK)
+                        corr = mask_weights(ca[c][k] - KT_MARGIN + p.bx0, y0, W, H, wx0, wx1, wy0, wy1,
+                                            (uint32_t)e.bval_i);
+                    uint32_t v[C];
+                    interp_u8<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1],
+                                 MASK ? (wx0 | (wx1 << 16)) : cw[c][k], wy0 << 2, wy1 << 2, v);
+                    if (MASK) {
+#pragma unroll
+                        for (int q = 0; q < C; q++)
+                            v[q] += corr;
+                    }
+                    P[k] = pack_px<C>(v);
+                }
+                store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + row_off, xr, x_end, aligned, P, sel);
+            } else {
+                const float fy = __builtin_bit_cast(float, rw);
+                float o[PX][C];
+#pragma unroll
+                for (int k = 0; k < PX; k++) {
+                    const int a = s0 + ca[c][k];
+                    const float fx = __builtin_bit_cast(float, cw[c][k]);
+                    float wx0 = 1.0f - fx, wx1 = fx, wy0 = 1.0f - fy, wy1 = fy, extra = 0.0f;
+                    if (MASK) {
+                        const int x0 = ca[c][k] - KT_MARGIN + p.bx0;
+                        wx0 = (unsigned)x0 < (unsigned)W ? wx0 : 0.0f;
+                        wx1 = (unsigned)(x0 + 1) < (unsigned)W ? wx1 : 0.0f;
+                        wy0 = vy0 ? wy0 : 0.0f;
+                        wy1 = vy1 ? wy1 : 0.0f;
+                        extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
+                    }
+                    interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
+                                  e, o[k]);
+                }
+                store_run_f32<C, PX>(static_cast<float *>(j.dst) + row_off, xr, x_end, aligned, o);
+            }
+        }
+    }
+}
+
+template <int C, bool F32, class L>
+__device__ __forceinline__ void compute_resize(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
+                                               const uint32_t *lds)
+{
+    if (!p.inside && e.border == KR_BORDER_CONSTANT)
+        compute_resize_t<C, F32, L, true>(t, p, G, e, lds);
+    else
+        compute_resize_t<C, F32, L, false>(t, p, G, e, lds);
+}
+
+// ------------------------------------------------------------------ tile pipeline
+// Stage -> (edge fill) -> issue the next tile's loads -> compute this tile.
+// The next tile's global loads stay in flight in registers while this tile is
+// interpolated from LDS.
+template <int OP, int C, bool F32, class L, int MAXIT, typename NextJob>
+__device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, uint32_t *lds, NextJob next_job)
+{
+    constexpr int TW = L::TW;
+    constexpr int TH = L::TH;
+    TiledJob t;
+    int tile;
+    if (!next_job(t, tile))
+        return;
+    Plan p = make_plan<OP, TW, TH, F32>(t, tile, G);
+    Prefetch<C, MAXIT> pf;
+    prefetch<OP, C, MAXIT>(t, p, G, pf);
+    while (true) {
+        if (!p.direct) {
+            commit<OP, C, MAXIT>(t, p, G, pf, lds);
+            if constexpr (OP == OP_RESIZE)
+                resize_tables<TW, TH, F32>(t, p, G, lds);
+        }
+        __syncthreads();
+        if (needs_edge_fill(t, p, e)) {
+            fill_edge_columns<OP, C>(t, p, G, lds);
+            __syncthreads();
+        }
+        TiledJob nt;
+        int ntile;
+        const bool more = next_job(nt, ntile);
+        Plan np;
+        if (more) {
+            np = make_plan<OP, TW, TH, F32>(nt, ntile, G);
+            prefetch<OP, C, MAXIT>(nt, np, G, pf);
+        }
+        if (p.direct)
+            compute_direct<OP, C, F32, L>(t, p, e);
+        else if constexpr (OP == OP_RESIZE)
+            compute_resize<C, F32, L>(t, p, G, e, lds);
+        else
+            compute_warp<C, F32, L>(t, p, G, e, lds);
+        if (!more)
+            break;
+        __syncthreads();
+        t = nt;
+        p = np;
+    }
+}
+
+// Static schedule of a persistent grid over n tiles, XCD-aware: blocks are
+// dealt to the 8 XCDs round-robin, so XCD k (blocks b = k mod 8) owns the k-th
+// contiguous eighth of the tiles and its blocks interleave over it, keeping
+// neighbouring tiles (which share source rows) in one L2.  With one tile per
+// block it is the bijection xcd_tile(); otherwise the grid is a multiple of 8.
+struct TileSeq {
+    int next, step, end;
+    __device__ __forceinline__ TileSeq(int b, int grid, int n)
+    {
+        if (grid >= n) {
+            next = xcd_tile(b, n);
+            step = n;
+            end = n;
+        } else {
+            const int k = b & 7, q = n >> 3, r = n & 7;
+            const int start = k * q + (k < r ? k : r);
+            next = start + (b >> 3);
+            step = grid >> 3;
+            end = start + q + (k < r ? 1 : 0);
+        }
+    }
+    __device__ __forceinline__ bool take(int &tile)
+    {
+        if (next >= end)
+            return false;
+        tile = next;
+        next += step;
+        return true;
+    }
+};
+
+}  // namespace kr

@@ -1,0 +1,209 @@
+// tiled.hip -- per-image launches of the LDS-tiled kernels (tiled.h): tile
+// shape, LDS budget and grid for one image.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "tiled.h"
+#include "tiled_launch.h"
+
+namespace kr {
+
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT>
+__global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, TileGeom G)
+{
+    extern __shared__ uint32_t lds[];
+    TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT>(G, e, lds, [&](TiledJob &t, int &tile) {
+        if (!seq.take(tile))
+            return false;
+        t = job;
+        return true;
+    });
+}
+
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+// Resident workgroups per CU for a kernel at a dynamic LDS size, cached per
+// kernel and kilobyte of LDS.
+template <typename K>
+static int blocks_per_cu(K kernel, size_t lds)
+{
+    static int cache[65] = {0};
+    const size_t slot = (lds + 1023) / 1024;
+    if (slot > 64)
+        return 1;
+    if (cache[slot] == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, KT_THREADS, slot * 1024) != hipSuccess || n < 1)
+            n = 1;
+        cache[slot] = n;
+    }
+    return cache[slot];
+}
+
+int persistent_grid(int ntiles, int per_cu)
+{
+    const long resident = (long)per_cu * device_cus();
+    if (resident >= ntiles)
+        return ntiles;
+    int g = (int)resident & ~7;
+    return g < 8 ? 8 : g;
+}
+
+TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th)
+{
+    TiledJob t;
+    t.j = j;
+    for (int i = 0; i < 6; i++)
+        t.m2048[i] = 2048.0 * j.inv[i];
+    t.op = op;
+    t.tiles_x = (j.dw + tw - 1) / tw;
+    t.ntiles = t.tiles_x * ((j.dh + th - 1) / th);
+    t.first_tile = 0;
+    return t;
+}
+
+// LDS pitch rounded up to 17 (mod 32) dwords: slots then start on banks that
+// differ for 32 consecutive slots (staging writes) and neighbouring tap rows
+// fall on different banks (gathers).
+static int bank_pitch(int pitch) { return pitch + ((17 - pitch % 32) + 32) % 32; }
+
+TileGeom tile_geom(const ImageJob &j, int op, int tw, int th)
+{
+    TileGeom G;
+    if (op == OP_WARP) {
+        const double ex = std::fabs(j.inv[0]) * (tw - 1) + std::fabs(j.inv[1]) * (th - 1);
+        const double ey = std::fabs(j.inv[3]) * (tw - 1) + std::fabs(j.inv[4]) * (th - 1);
+        G.pitch = (int)std::fmin(std::ceil(ex) + 4.0, (double)j.sw + 6.0) + 2 * KT_MARGIN;
+        G.rows = (int)std::fmin(std::ceil(ey) + 4.0, (double)j.sh + 6.0);
+        G.pitch = bank_pitch(G.pitch);
+    } else {
+        const double rx = (double)j.sw / (double)j.dw;
+        G.pitch = (int)std::fmin(std::ceil(rx * (tw - 1)) + 3.0, (double)j.sw + 4.0) + 2 * KT_MARGIN;
+        G.rows = 2 * th;
+        G.pitch = bank_pitch(G.pitch);
+    }
+    return G;
+}
+
+size_t tile_lds_bytes(const TileGeom &G, int tw, int th)
+{
+    return (size_t)G.rows * G.pitch * 4 + (size_t)(2 * tw + 2 * th) * 4;
+}
+
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
+static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s, bool persistent, bool &fits)
+{
+    using L = Layout<PX, TXT, CPT, RPT>;
+    constexpr int TW = L::TW, TH = L::TH, MAXIT = 3;
+    const TiledJob t = make_tiled_job(j, OP, TW, TH);
+    const TileGeom G = tile_geom(j, OP, TW, TH);
+    const size_t lds = tile_lds_bytes(G, TW, TH);
+    fits = lds <= KT_LDS_CAP;
+    if (!fits)
+        return hipSuccess;
+    auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT>;
+    const int grid = persistent ? persistent_grid(t.ntiles, blocks_per_cu(kern, lds)) : t.ntiles;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
+    return hipGetLastError();
+}
+
+// Tile configurations (PX, TXT, CPT, RPT) compiled per operation.
+#define KR_WARP_CFGS(X) X(4, 16, 1, 2) X(4, 16, 1, 4) X(1, 64, 1, 8) X(1, 64, 1, 16)
+#define KR_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 32, 1, 2) X(4, 64, 1, 1) X(4, 64, 1, 2) \
+    X(1, 64, 2, 4) X(1, 64, 4, 2)
+
+template <int OP, int C, bool F32>
+static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epilogue &e, hipStream_t s, bool &fits)
+{
+#define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
+    if (cfg.px == PX && cfg.txt == TXT && cfg.cpt == CPT && cfg.rpt == RPT)                              \
+        return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.persistent, fits);
+    if constexpr (OP == OP_WARP) {
+        KR_WARP_CFGS(KR_TRY)
+    } else {
+        KR_RESIZE_CFGS(KR_TRY)
+    }
+#undef KR_TRY
+    fits = false;
+    return hipSuccess;
+}
+
+// Tile shapes tried in order (the first whose LDS footprint fits is used).
+// KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent" override the
+// first choice.
+static int default_cfgs(int op, bool f32, TileCfg *out)
+{
+    int n = 0;
+    const char *tile = std::getenv("KR_TILE");
+    const char *grid = std::getenv("KR_GRID");
+    const bool force_full = grid && std::strcmp(grid, "full") == 0;
+    const bool force_pers = grid && std::strcmp(grid, "persistent") == 0;
+    int px = 0, txt = 0, cpt = 0, rpt = 0;
+    if (tile && std::sscanf(tile, "%dx%dx%dx%d", &px, &txt, &cpt, &rpt) == 4)
+        out[n++] = TileCfg{px, txt, cpt, rpt, !force_full};
+    auto add = [&](int a, int b, int c, int d, bool pers) {
+        out[n++] = TileCfg{a, b, c, d, force_pers ? true : (force_full ? false : pers)};
+    };
+    // measured on MI355X for 4K sources (3840x2160x3 u8)
+    if (op == OP_WARP) {
+        if (f32) {
+            add(1, 64, 1, 16, true);
+            add(1, 64, 1, 8, true);
+        } else {
+            add(4, 16, 1, 4, true);
+            add(4, 16, 1, 2, true);
+        }
+        add(1, 64, 1, 8, true);
+    } else {
+        add(1, 64, 2, 4, true);
+        add(4, 16, 1, 1, true);
+    }
+    return n;
+}
+
+template <int OP, int C, bool F32>
+static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
+{
+    TileCfg cfgs[6];
+    const int n = default_cfgs(OP, F32, cfgs);
+    for (int i = 0; i < n; i++) {
+        bool fits = false;
+        const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, fits);
+        if (fits || err != hipSuccess)
+            return err;
+    }
+    return launch_generic(OP, C, KR_U8, F32 ? KR_F32 : KR_U8, j, e, s);
+}
+
+bool tiled_supported(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 4); }
+
+hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
+{
+    const bool f = dt == KR_F32;
+    if (op == OP_WARP) {
+        if (c == 3)
+            return f ? launch_c<OP_WARP, 3, true>(j, e, s) : launch_c<OP_WARP, 3, false>(j, e, s);
+        return f ? launch_c<OP_WARP, 4, true>(j, e, s) : launch_c<OP_WARP, 4, false>(j, e, s);
+    }
+    if (c == 3)
+        return f ? launch_c<OP_RESIZE, 3, true>(j, e, s) : launch_c<OP_RESIZE, 3, false>(j, e, s);
+    return f ? launch_c<OP_RESIZE, 4, true>(j, e, s) : launch_c<OP_RESIZE, 4, false>(j, e, s);
+}
+
+}  // namespace kr
