@@ -20,8 +20,9 @@ LIB = os.path.join(PKG, "libkr.so")
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are kept off: the compiler would otherwise form
-# them from plain float code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# them from plain float code.  No floating-point contraction: every fma is
+# written explicitly, so all kernel variants round identically.
+DEVICE_FLAGS = ["-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC, "-Wall", "-Wno-unused-function"]
 

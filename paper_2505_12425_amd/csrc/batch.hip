@@ -1,0 +1,377 @@
+// batch.hip -- many resizes / warps of uneven sizes in one launch per
+// operation: the kernel walks a work-list of output tiles spanning every
+// image.  Image i owns global tiles [first_tile_i, first_tile_i + ntiles_i);
+// a tile finds its image by binary search over first_tile.  The per-tile work
+// is exactly the single-image kernels' (tiled.h), so every image's output is
+// bit-identical to its single-image call.
+//
+// Host side: validation, the tile list (prefix sums of per-image tile
+// counts), the launch-wide LDS geometry, the C ABI entry points
+// kr_resize_batch / kr_batch_plan_* (plans capture their launches in a HIP
+// graph; they record no memset nodes).
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kr_api_internal.h"
+#include "tiled.h"
+#include "tiled_launch.h"
+
+namespace kr {
+
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT>
+__global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict__ jobs, int njobs, int ntiles,
+                                                      Epilogue e, TileGeom G)
+{
+    extern __shared__ uint32_t lds[];
+    TileSeq seq(blockIdx.x, gridDim.x, ntiles);
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT>(G, e, lds, [&](TiledJob &t, int &tile) {
+        int g;
+        if (!seq.take(g))
+            return false;
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].first_tile <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        t = jobs[lo];
+        tile = g - t.first_tile;
+        return true;
+    });
+}
+
+// One operation group of a batch, ready to launch.
+struct BatchGroup {
+    int op = OP_RESIZE;
+    TileCfg cfg{4, 16, 1, 1, false};
+    TileGeom G{0, 0};
+    int njobs = 0;
+    int ntiles = 0;
+    size_t lds = 0;
+    const TiledJob *jobs_dev = nullptr;  // device copy of the job table
+};
+
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
+static hipError_t launch_group_cfg(const BatchGroup &g, const Epilogue &e, hipStream_t s)
+{
+    auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 3>;
+    int grid = g.ntiles;
+    if (g.cfg.persistent) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, KT_THREADS, g.lds) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        grid = persistent_grid(g.ntiles, per_cu);
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.ntiles, e, g.G);
+    return hipGetLastError();
+}
+
+// Batched tile configurations (PX, TXT, CPT, RPT).
+#define KR_BATCH_WARP_CFGS(X) X(4, 16, 1, 1) X(4, 16, 1, 2) X(1, 64, 1, 4) X(1, 64, 1, 8)
+#define KR_BATCH_RESIZE_CFGS(X) X(4, 16, 1, 1) X(1, 64, 1, 4) X(1, 64, 2, 4)
+
+template <int OP, int C, bool F32>
+static hipError_t launch_group_c(const BatchGroup &g, const Epilogue &e, hipStream_t s)
+{
+#define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
+    if (g.cfg.px == PX && g.cfg.txt == TXT && g.cfg.cpt == CPT && g.cfg.rpt == RPT)                      \
+        return launch_group_cfg<OP, C, F32, PX, TXT, CPT, RPT>(g, e, s);
+    if constexpr (OP == OP_WARP) {
+        KR_BATCH_WARP_CFGS(KR_TRY)
+    } else {
+        KR_BATCH_RESIZE_CFGS(KR_TRY)
+    }
+#undef KR_TRY
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue &e, hipStream_t s)
+{
+    if (g.njobs == 0)
+        return hipSuccess;
+    const bool f = dt == KR_F32;
+    if (g.op == OP_WARP) {
+        if (c == 3)
+            return f ? launch_group_c<OP_WARP, 3, true>(g, e, s) : launch_group_c<OP_WARP, 3, false>(g, e, s);
+        return f ? launch_group_c<OP_WARP, 4, true>(g, e, s) : launch_group_c<OP_WARP, 4, false>(g, e, s);
+    }
+    if (c == 3)
+        return f ? launch_group_c<OP_RESIZE, 3, true>(g, e, s) : launch_group_c<OP_RESIZE, 3, false>(g, e, s);
+    return f ? launch_group_c<OP_RESIZE, 4, true>(g, e, s) : launch_group_c<OP_RESIZE, 4, false>(g, e, s);
+}
+
+// Tile shape of a batch group (small tiles: batches of small outputs still
+// produce many tiles; shrinking warps keep boxes small).
+static TileCfg batch_cfg(int op, bool f32)
+{
+    if (op == OP_WARP)
+        return f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false};
+    return f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false};
+}
+
+constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's widest box
+
+// Build the host-side job table of one operation group.  Items whose own box
+// would exceed the LDS budget (and large-ratio resizes) run every tile on the
+// global-gather path; the others set the launch-wide LDS geometry.
+static void build_group(int op, bool f32, const std::vector<ImageJob> &imgs, BatchGroup &g,
+                        std::vector<TiledJob> &table)
+{
+    g.op = op;
+    g.cfg = batch_cfg(op, f32);
+    const int tw = g.cfg.txt * g.cfg.px * g.cfg.cpt;
+    const int th = (KT_THREADS / g.cfg.txt) * g.cfg.rpt;
+    table.clear();
+    g.G = TileGeom{0, 0};
+    int first = 0;
+    for (const ImageJob &j : imgs) {
+        TiledJob t = make_tiled_job(j, op, tw, th);
+        t.first_tile = first;
+        first += t.ntiles;
+        table.push_back(t);
+        const TileGeom Gi = tile_geom(j, op, tw, th);
+        if (wants_gather(j, op) || tile_lds_bytes(Gi, tw, th) > KB_LDS_BUDGET)
+            continue;
+        g.G.pitch = std::max(g.G.pitch, Gi.pitch);
+        g.G.rows = std::max(g.G.rows, Gi.rows);
+    }
+    g.njobs = (int)table.size();
+    g.ntiles = first;
+    g.lds = tile_lds_bytes(g.G, tw, th);
+}
+
+}  // namespace kr
+
+using namespace kr;
+
+// ------------------------------------------------------------------ validation
+static kr_status check_items(const kr_batch_item *items, int n, int c, kr_dtype st, kr_dtype dt, kr_border border,
+                             float bval, const kr_normalize *norm, std::vector<ImageJob> &rs,
+                             std::vector<ImageJob> &ws)
+{
+    if (!items && n > 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "items pointer is NULL");
+    if (n < 0 || n > (1 << 20))
+        return fail(KR_ERR_INVALID_ARGUMENT, "item count %d out of range", n);
+    rs.clear();
+    ws.clear();
+    for (int i = 0; i < n; i++) {
+        const kr_batch_item &it = items[i];
+        kr_status s = check_common(it.src, it.src_h, it.src_w, c, st, it.dst, it.dst_h, it.dst_w, dt, border, bval,
+                                   norm);
+        if (s != KR_OK)
+            return fail(s, "item %d: %s", i, kr_last_error());
+        if (it.op != KR_OP_RESIZE && it.op != KR_OP_WARP)
+            return fail(KR_ERR_INVALID_ARGUMENT, "item %d: unknown op %d", i, it.op);
+        ImageJob j;
+        std::memset(&j, 0, sizeof j);
+        j.src = it.src; j.dst = it.dst;
+        j.sh = it.src_h; j.sw = it.src_w; j.dh = it.dst_h; j.dw = it.dst_w;
+        if (it.op == KR_OP_WARP) {
+            if (it.flags & ~KR_WARP_INVERSE_MAP)
+                return fail(KR_ERR_INVALID_ARGUMENT, "item %d: unknown warp flags 0x%x", i, it.flags);
+            s = check_matrix(it.m, it.flags, j.inv);
+            if (s != KR_OK)
+                return fail(s, "item %d: %s", i, kr_last_error());
+            ws.push_back(j);
+        } else {
+            rs.push_back(j);
+        }
+    }
+    // destinations must not overlap each other or any source
+    const size_t es_d = dt == KR_U8 ? 1 : 4, es_s = st == KR_U8 ? 1 : 4;
+    struct R { uintptr_t a, b; };
+    std::vector<R> dsts, srcs;
+    for (int i = 0; i < n; i++) {
+        const uintptr_t d = reinterpret_cast<uintptr_t>(items[i].dst);
+        dsts.push_back({d, d + (uintptr_t)items[i].dst_h * items[i].dst_w * c * es_d});
+        const uintptr_t s0 = reinterpret_cast<uintptr_t>(items[i].src);
+        srcs.push_back({s0, s0 + (uintptr_t)items[i].src_h * items[i].src_w * c * es_s});
+    }
+    std::vector<R> sd = dsts;
+    std::sort(sd.begin(), sd.end(), [](const R &x, const R &y) { return x.a < y.a; });
+    for (size_t i = 1; i < sd.size(); i++)
+        if (sd[i].a < sd[i - 1].b)
+            return fail(KR_ERR_INVALID_ARGUMENT, "batch destinations overlap");
+    std::vector<R> ss = srcs;
+    std::sort(ss.begin(), ss.end(), [](const R &x, const R &y) { return x.a < y.a; });
+    for (const R &d : sd) {
+        // first source starting at or after d.b cannot overlap; check its predecessors
+        auto it = std::lower_bound(ss.begin(), ss.end(), d.b, [](const R &x, uintptr_t v) { return x.a < v; });
+        for (auto k = ss.begin(); k != it; ++k)
+            if (k->b > d.a)
+                return fail(KR_ERR_INVALID_ARGUMENT, "a batch destination overlaps a source");
+    }
+    return KR_OK;
+}
+
+// Device layout of a batch workspace: the resize group's job table, then the
+// warp group's, each 256-byte aligned.
+static size_t table_bytes(int n) { return ((size_t)n * sizeof(TiledJob) + 255) & ~(size_t)255; }
+
+extern "C" {
+
+size_t kr_resize_batch_workspace_size(int n) { return n > 0 ? 2 * table_bytes(n) : 256; }
+
+kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t, kr_border border,
+                          float border_value, const kr_normalize *norm, void *workspace, size_t workspace_bytes,
+                          void *stream)
+{
+    clear_error();
+    std::vector<ImageJob> rs, ws;
+    kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, rs, ws);
+    if (st != KR_OK)
+        return st;
+    if (n == 0)
+        return KR_OK;
+    if (!tiled_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+    if (workspace_bytes < kr_resize_batch_workspace_size(n))
+        return fail(KR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", workspace_bytes,
+                    kr_resize_batch_workspace_size(n));
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    hipStream_t s = (hipStream_t)stream;
+    const bool f32 = dst_t == KR_F32;
+    uint8_t *wsb = static_cast<uint8_t *>(workspace);
+    BatchGroup groups[2];
+    std::vector<TiledJob> tables[2];
+    build_group(OP_RESIZE, f32, rs, groups[0], tables[0]);
+    build_group(OP_WARP, f32, ws, groups[1], tables[1]);
+    size_t off = 0;
+    for (int k = 0; k < 2; k++) {
+        if (groups[k].njobs == 0)
+            continue;
+        TiledJob *dev = reinterpret_cast<TiledJob *>(wsb + off);
+        off += table_bytes(groups[k].njobs);
+        // pageable source: the runtime stages it before the call returns
+        hipError_t err = hipMemcpyAsync(dev, tables[k].data(), tables[k].size() * sizeof(TiledJob),
+                                        hipMemcpyHostToDevice, s);
+        if (err != hipSuccess)
+            return fail(KR_ERR_HIP, "work-list upload failed: %s", hipGetErrorString(err));
+        groups[k].jobs_dev = dev;
+        err = launch_group(groups[k], c, dst_t, e, s);
+        if (err != hipSuccess)
+            return fail(KR_ERR_HIP, "batch launch failed: %s", hipGetErrorString(err));
+    }
+    return KR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+struct kr_batch_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *table = nullptr;  // device job tables
+    int ntiles = 0;
+};
+
+static void plan_free(kr_batch_plan *p)
+{
+    if (!p)
+        return;
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->table)
+        (void)hipFree(p->table);
+    delete p;
+}
+
+extern "C" {
+
+kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                               kr_border border, float border_value, const kr_normalize *norm, kr_batch_plan **plan)
+{
+    clear_error();
+    if (!plan)
+        return fail(KR_ERR_INVALID_ARGUMENT, "plan pointer is NULL");
+    *plan = nullptr;
+    std::vector<ImageJob> rs, ws;
+    kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, rs, ws);
+    if (st != KR_OK)
+        return st;
+    if (n == 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "a plan needs at least one item");
+    if (!tiled_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    const bool f32 = dst_t == KR_F32;
+    kr_batch_plan *p = new (std::nothrow) kr_batch_plan();
+    if (!p)
+        return fail(KR_ERR_INVALID_ARGUMENT, "out of host memory");
+    BatchGroup groups[2];
+    std::vector<TiledJob> tables[2];
+    build_group(OP_RESIZE, f32, rs, groups[0], tables[0]);
+    build_group(OP_WARP, f32, ws, groups[1], tables[1]);
+    const size_t bytes = kr_resize_batch_workspace_size(n);
+    hipError_t err = hipMalloc(&p->table, bytes);
+    if (err != hipSuccess) {
+        plan_free(p);
+        return fail(KR_ERR_HIP, "plan allocation failed: %s", hipGetErrorString(err));
+    }
+    size_t off = 0;
+    for (int k = 0; k < 2; k++) {
+        if (groups[k].njobs == 0)
+            continue;
+        TiledJob *dev = reinterpret_cast<TiledJob *>(static_cast<uint8_t *>(p->table) + off);
+        off += table_bytes(groups[k].njobs);
+        err = hipMemcpy(dev, tables[k].data(), tables[k].size() * sizeof(TiledJob), hipMemcpyHostToDevice);
+        if (err != hipSuccess) {
+            plan_free(p);
+            return fail(KR_ERR_HIP, "plan upload failed: %s", hipGetErrorString(err));
+        }
+        groups[k].jobs_dev = dev;
+        p->ntiles += groups[k].ntiles;
+    }
+    hipStream_t cs = nullptr;
+    err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (err == hipSuccess)
+        err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+        hipError_t lerr = hipSuccess;
+        for (int k = 0; k < 2 && lerr == hipSuccess; k++)
+            lerr = launch_group(groups[k], c, dst_t, e, cs);
+        err = hipStreamEndCapture(cs, &p->graph);
+        if (err == hipSuccess)
+            err = lerr;
+    }
+    if (err == hipSuccess)
+        err = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (err != hipSuccess) {
+        plan_free(p);
+        return fail(KR_ERR_HIP, "plan graph capture failed: %s", hipGetErrorString(err));
+    }
+    *plan = p;
+    return KR_OK;
+}
+
+kr_status kr_batch_plan_launch(kr_batch_plan *plan, void *stream)
+{
+    clear_error();
+    if (!plan || !plan->exec)
+        return fail(KR_ERR_INVALID_ARGUMENT, "plan is NULL");
+    const hipError_t err = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "plan launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
+void kr_batch_plan_destroy(kr_batch_plan *plan)
+{
+    if (!plan)
+        return;
+    (void)hipDeviceSynchronize();
+    plan_free(plan);
+}
+
+}  // extern "C"

@@ -77,6 +77,19 @@ __device__ __forceinline__ void warp_axis(double s, int n, int &i0, int &w1, flo
     f = (float)fr;
 }
 
+// f32 bilinear blend of four taps with per-axis weights, plus `extra` (the
+// border's share under a CONSTANT border), then the affine epilogue
+// out = v * alpha + beta.  One fixed order of explicit fma so that every
+// kernel computes identical bits.
+__device__ __forceinline__ float blend_f32(float p00, float p01, float p10, float p11, float wx0, float wx1, float wy0,
+                                           float wy1, float extra, float alpha, float beta)
+{
+    const float top = __builtin_fmaf(wx1, p01, wx0 * p00);
+    const float bot = __builtin_fmaf(wx1, p11, wx0 * p10);
+    const float v = __builtin_fmaf(wy1, bot, wy0 * top) + extra;
+    return __builtin_fmaf(v, alpha, beta);
+}
+
 // One tap of C channels as integers (u8 source) with the border rule.
 template <int C, typename S>
 __device__ __forceinline__ void tap_int(const S *src, int h, int w, int x, int y, const Epilogue &e, int (&p)[C])
@@ -164,12 +177,9 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
         tap_float<C>(src, j.sh, j.sw, x0, y0 + 1, e, p10);
         tap_float<C>(src, j.sh, j.sw, x0 + 1, y0 + 1, e, p11);
 #pragma unroll
-        for (int c = 0; c < C; c++) {
-            const float top = (1.0f - fx) * p00[c] + fx * p01[c];
-            const float bot = (1.0f - fx) * p10[c] + fx * p11[c];
-            const float v = (1.0f - fy) * top + fy * bot;
-            dst[c] = v * e.alpha[c] + e.beta[c];
-        }
+        for (int c = 0; c < C; c++)
+            dst[c] = blend_f32(p00[c], p01[c], p10[c], p11[c], 1.0f - fx, fx, 1.0f - fy, fy, 0.0f, e.alpha[c],
+                               e.beta[c]);
     }
 }
 

@@ -133,6 +133,8 @@ __device__ __forceinline__ uint32_t mask_weights(int x0, int y0, int W, int H, u
 }
 
 // f32 interpolation with unquantised weights, then out = v * alpha + beta.
+// The operation order is fixed (explicit fma, no contraction), so every kernel
+// path produces the same bits.
 template <int C>
 __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t t10, uint32_t t11, float wx0,
                                            float wx1, float wy0, float wy1, float extra, const Epilogue &e,
@@ -144,10 +146,7 @@ __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t 
         const float p01 = (float)((t01 >> (8 * c)) & 0xFFu);
         const float p10 = (float)((t10 >> (8 * c)) & 0xFFu);
         const float p11 = (float)((t11 >> (8 * c)) & 0xFFu);
-        const float top = wx0 * p00 + wx1 * p01;
-        const float bot = wx0 * p10 + wx1 * p11;
-        const float v = wy0 * top + wy1 * bot + extra;
-        o[c] = v * e.alpha[c] + e.beta[c];
+        o[c] = blend_f32(p00, p01, p10, p11, wx0, wx1, wy0, wy1, extra, e.alpha[c], e.beta[c]);
     }
 }
 
@@ -616,27 +615,6 @@ __device__ __forceinline__ bool layout_aligned(int dw)
         return F32 || C == 4 || (((size_t)dw * C) & 3) == 0;
 }
 
-template <int OP, int C, bool F32, class L>
-__device__ __forceinline__ void compute_direct(const TiledJob &t, const Plan &p, const Epilogue &e)
-{
-    for (int r = 0; r < L::RPT; r++) {
-        const int y = p.oy0 + L::row0() + r * L::ROWS;
-        if (y > p.oy1)
-            break;
-        for (int c = 0; c < L::CPT; c++) {
-            for (int k = 0; k < L::PX; k++) {
-                const int x = p.ox0 + c * L::SEG + L::col0() + k;
-                if (x > p.ox1)
-                    continue;
-                if constexpr (F32)
-                    generic_pixel<C, uint8_t, float, OP>(t.j, e, x, y);
-                else
-                    generic_pixel<C, uint8_t, uint8_t, OP>(t.j, e, x, y);
-            }
-        }
-    }
-}
-
 template <int C, bool F32, class L, bool CLAMP, bool MASK>
 __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                                const uint32_t *lds)
@@ -832,6 +810,181 @@ __device__ __forceinline__ void compute_resize(const TiledJob &t, const Plan &p,
         compute_resize_t<C, F32, L, false>(t, p, G, e, lds);
 }
 
+// ------------------------------------------------------------------ gather path
+// Tiles whose box does not fit the LDS budget (and resizes with large
+// down-sampling ratios, where neighbouring outputs share no taps) read their
+// taps straight from global memory: per tap row, the two horizontal taps are
+// 2 * C contiguous bytes, loaded as one dword-aligned 12-byte (RGB) or 8-byte
+// (RGBA) read and realigned with byte-align ops.  Taps outside the image take
+// the border rule per tap.
+
+// The two horizontal taps at (x0, y) and (x0 + 1, y), both inside the image,
+// as pixel dwords (byte c = channel c; RGB byte 3 unspecified).
+template <int C>
+__device__ __forceinline__ void load_tap_pair(const uint8_t *__restrict__ src, size_t nbytes, size_t lin, uint32_t &t0,
+                                              uint32_t &t1)
+{
+    if constexpr (C == 4) {
+        struct __attribute__((packed, aligned(4))) D2 { uint32_t a, b; };
+        const D2 d = *reinterpret_cast<const D2 *>(src + lin * 4);
+        t0 = d.a;
+        t1 = d.b;
+    } else {
+        const size_t b = lin * 3;
+        const size_t f = b & ~(size_t)3;
+        if (f + 12 <= nbytes) {
+            struct __attribute__((packed, aligned(4))) D3 { uint32_t a, b, c; };
+            const D3 d = *reinterpret_cast<const D3 *>(src + f);
+            const uint32_t sh = (uint32_t)(b & 3);
+            const uint32_t lo = __builtin_amdgcn_alignbyte(d.b, d.a, sh);
+            const uint32_t hi = __builtin_amdgcn_alignbyte(d.c, d.b, sh);
+            t0 = lo;
+            t1 = __builtin_amdgcn_alignbyte(hi, lo, 3);
+        } else {
+            t0 = load_px_bytes<3>(src, lin);
+            t1 = load_px_bytes<3>(src, lin + 1);
+        }
+    }
+}
+
+// The four taps of a pixel with top-left tap (x0, y0).  Returns false when a
+// tap lies outside the image; the taps then hold the clamped (edge) pixels,
+// which is the REPLICATE rule, and a CONSTANT border masks their weights.
+template <int C>
+__device__ __forceinline__ bool load_taps(const uint8_t *__restrict__ src, int W, int H, int x0, int y0, uint32_t &t00,
+                                          uint32_t &t01, uint32_t &t10, uint32_t &t11)
+{
+    const size_t nbytes = (size_t)W * H * C;
+    if ((unsigned)x0 < (unsigned)(W - 1) && (unsigned)y0 < (unsigned)(H - 1)) {
+        const size_t lin = (size_t)y0 * W + x0;
+        load_tap_pair<C>(src, nbytes, lin, t00, t01);
+        load_tap_pair<C>(src, nbytes, lin + W, t10, t11);
+        return true;
+    }
+    const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+    const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+    t00 = load_px_bytes<C>(src, (size_t)ya * W + xa);
+    t01 = load_px_bytes<C>(src, (size_t)ya * W + xb);
+    t10 = load_px_bytes<C>(src, (size_t)yb * W + xa);
+    t11 = load_px_bytes<C>(src, (size_t)yb * W + xb);
+    return false;
+}
+
+// u8 result of one pixel from global taps.
+template <int C>
+__device__ __forceinline__ uint32_t gather_px_u8(const ImageJob &j, const Epilogue &e, int x0, int y0, uint32_t wx1,
+                                                 uint32_t wy1)
+{
+    uint32_t t00, t01, t10, t11;
+    const bool in = load_taps<C>(static_cast<const uint8_t *>(j.src), j.sw, j.sh, x0, y0, t00, t01, t10, t11);
+    uint32_t wx0 = 2048u - wx1, wy0 = 2048u - wy1, corr = 0;
+    if (!in && e.border == KR_BORDER_CONSTANT)
+        corr = mask_weights(x0, y0, j.sw, j.sh, wx0, wx1, wy0, wy1, (uint32_t)e.bval_i);
+    uint32_t v[C];
+    interp_u8<C>(t00, t01, t10, t11, wx0 | (wx1 << 16), wy0 << 2, wy1 << 2, v);
+#pragma unroll
+    for (int q = 0; q < C; q++)
+        v[q] += corr;
+    return pack_px<C>(v);
+}
+
+template <int C>
+__device__ __forceinline__ void gather_px_f32(const ImageJob &j, const Epilogue &e, int x0, int y0, float fx, float fy,
+                                              float (&o)[C])
+{
+    uint32_t t00, t01, t10, t11;
+    const bool in = load_taps<C>(static_cast<const uint8_t *>(j.src), j.sw, j.sh, x0, y0, t00, t01, t10, t11);
+    float wx0 = 1.0f - fx, wx1 = fx, wy0 = 1.0f - fy, wy1 = fy, extra = 0.0f;
+    if (!in && e.border == KR_BORDER_CONSTANT) {
+        const int W = j.sw, H = j.sh;
+        wx0 = (unsigned)x0 < (unsigned)W ? wx0 : 0.0f;
+        wx1 = (unsigned)(x0 + 1) < (unsigned)W ? wx1 : 0.0f;
+        wy0 = (unsigned)y0 < (unsigned)H ? wy0 : 0.0f;
+        wy1 = (unsigned)(y0 + 1) < (unsigned)H ? wy1 : 0.0f;
+        extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
+    }
+    interp_f32<C>(t00, t01, t10, t11, wx0, wx1, wy0, wy1, extra, e, o);
+}
+
+template <int OP, int C, bool F32, class L>
+__device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
+                                               const uint32_t *lds)
+{
+    constexpr int PX = L::PX, CPT = L::CPT, TW = L::TW, TH = L::TH;
+    const ImageJob &j = t.j;
+    const bool aligned = layout_aligned<C, F32, L>(j.dw);
+    const uint32_t sel = quad_selector(lane_id() & 3);
+    const int x_end = p.ox1 + 1;
+    const uint32_t *tab = lds + G.rows * G.pitch;
+    double m[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++)
+        m[i] = F32 ? j.inv[i] : t.m2048[i];
+    for (int r = 0; r < L::RPT; r++) {
+        const int rr = L::row0() + r * L::ROWS;
+        const int y = p.oy0 + rr;
+        if (y > p.oy1)
+            break;
+        const size_t row_off = (size_t)y * (size_t)j.dw * C;
+        double rowX = 0, rowY = 0;
+        int ry0 = 0;
+        uint32_t rw = 0;
+        if constexpr (OP == OP_WARP) {
+            rowX = __builtin_fma(m[1], (double)y, m[2]);
+            rowY = __builtin_fma(m[4], (double)y, m[5]);
+        } else {
+            ry0 = (int)tab[2 * TW + rr];
+            rw = tab[2 * TW + TH + rr];
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; c++) {
+            const int xr = p.ox0 + c * L::SEG + L::col0();
+            uint32_t P[PX];
+            float o[PX][C];
+#pragma unroll
+            for (int k = 0; k < PX; k++) {
+                const int cc = min(c * L::SEG + L::col0() + k, p.ox1 - p.ox0);
+                int x0, y0;
+                uint32_t wx1, wy1;
+                float fx, fy;
+                if constexpr (OP == OP_WARP) {
+                    const double xd = (double)(p.ox0 + cc);
+                    double X = __builtin_fma(m[0], xd, rowX);
+                    double Y = __builtin_fma(m[3], xd, rowY);
+                    if constexpr (!F32) {
+                        const int Nx = rne_i32(clamp_scaled(X, j.sw)), Ny = rne_i32(clamp_scaled(Y, j.sh));
+                        x0 = Nx >> 11; y0 = Ny >> 11;
+                        wx1 = (uint32_t)Nx & 2047u; wy1 = (uint32_t)Ny & 2047u;
+                        fx = fy = 0.0f;
+                    } else {
+                        X = clamp_plain(X, j.sw);
+                        Y = clamp_plain(Y, j.sh);
+                        const double fxl = __builtin_floor(X), fyl = __builtin_floor(Y);
+                        x0 = (int)fxl; y0 = (int)fyl;
+                        fx = (float)(X - fxl); fy = (float)(Y - fyl);
+                        wx1 = wy1 = 0;
+                    }
+                } else {
+                    x0 = (int)tab[cc] - KT_MARGIN + p.bx0;
+                    y0 = ry0;
+                    const uint32_t cw = tab[TW + cc];
+                    wx1 = cw >> 16; wy1 = rw;
+                    fx = __builtin_bit_cast(float, cw);
+                    fy = __builtin_bit_cast(float, rw);
+                }
+                if constexpr (!F32)
+                    P[k] = gather_px_u8<C>(j, e, x0, y0, wx1, wy1);
+                else
+                    gather_px_f32<C>(j, e, x0, y0, fx, fy, o[k]);
+            }
+            if constexpr (!F32)
+                store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + row_off, xr, x_end, aligned, P, sel);
+            else
+                store_run_f32<C, PX>(static_cast<float *>(j.dst) + row_off, xr, x_end, aligned, o);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ tile pipeline
 // Stage -> (edge fill) -> issue the next tile's loads -> compute this tile.
 // The next tile's global loads stay in flight in registers while this tile is
@@ -849,11 +1002,10 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
     Prefetch<C, MAXIT> pf;
     prefetch<OP, C, MAXIT>(t, p, G, pf);
     while (true) {
-        if (!p.direct) {
+        if (!p.direct)
             commit<OP, C, MAXIT>(t, p, G, pf, lds);
-            if constexpr (OP == OP_RESIZE)
-                resize_tables<TW, TH, F32>(t, p, G, lds);
-        }
+        if constexpr (OP == OP_RESIZE)
+            resize_tables<TW, TH, F32>(t, p, G, lds);
         __syncthreads();
         if (needs_edge_fill(t, p, e)) {
             fill_edge_columns<OP, C>(t, p, G, lds);
@@ -868,7 +1020,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
             prefetch<OP, C, MAXIT>(nt, np, G, pf);
         }
         if (p.direct)
-            compute_direct<OP, C, F32, L>(t, p, e);
+            compute_gather<OP, C, F32, L>(t, p, G, e, lds);
         else if constexpr (OP == OP_RESIZE)
             compute_resize<C, F32, L>(t, p, G, e, lds);
         else

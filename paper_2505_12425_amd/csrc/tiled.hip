@@ -101,18 +101,30 @@ TileGeom tile_geom(const ImageJob &j, int op, int tw, int th)
     return G;
 }
 
+// Resizes that shrink by more than 3x along x share no horizontal taps between
+// neighbouring outputs: staging buys no reuse, the taps are read directly.
+bool wants_gather(const ImageJob &j, int op)
+{
+    return op == OP_RESIZE && (double)j.sw > 3.0 * (double)j.dw;
+}
+
 size_t tile_lds_bytes(const TileGeom &G, int tw, int th)
 {
     return (size_t)G.rows * G.pitch * 4 + (size_t)(2 * tw + 2 * th) * 4;
 }
 
 template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
-static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s, bool persistent, bool &fits)
+static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s, bool persistent, bool gather,
+                             bool &fits)
 {
     using L = Layout<PX, TXT, CPT, RPT>;
     constexpr int TW = L::TW, TH = L::TH, MAXIT = 3;
     const TiledJob t = make_tiled_job(j, OP, TW, TH);
-    const TileGeom G = tile_geom(j, OP, TW, TH);
+    TileGeom G = tile_geom(j, OP, TW, TH);
+    if (gather || wants_gather(j, OP)) {
+        G.pitch = 0;  // no tile fits: every tile reads its taps from global memory
+        G.rows = 0;
+    }
     const size_t lds = tile_lds_bytes(G, TW, TH);
     fits = lds <= KT_LDS_CAP;
     if (!fits)
@@ -129,11 +141,12 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
     X(1, 64, 2, 4) X(1, 64, 4, 2)
 
 template <int OP, int C, bool F32>
-static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epilogue &e, hipStream_t s, bool &fits)
+static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epilogue &e, hipStream_t s, bool gather,
+                               bool &fits)
 {
 #define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
     if (cfg.px == PX && cfg.txt == TXT && cfg.cpt == CPT && cfg.rpt == RPT)                              \
-        return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.persistent, fits);
+        return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.persistent, gather, fits);
     if constexpr (OP == OP_WARP) {
         KR_WARP_CFGS(KR_TRY)
     } else {
@@ -184,11 +197,12 @@ static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
     const int n = default_cfgs(OP, F32, cfgs);
     for (int i = 0; i < n; i++) {
         bool fits = false;
-        const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, fits);
+        const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, false, fits);
         if (fits || err != hipSuccess)
             return err;
     }
-    return launch_generic(OP, C, KR_U8, F32 ? KR_F32 : KR_U8, j, e, s);
+    bool fits = false;
+    return launch_shape<OP, C, F32>(cfgs[n - 1], j, e, s, true, fits);
 }
 
 bool tiled_supported(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 4); }

@@ -24,5 +24,7 @@ int persistent_grid(int ntiles, int per_cu);
 TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th);
 TileGeom tile_geom(const ImageJob &j, int op, int tw, int th);
 size_t tile_lds_bytes(const TileGeom &G, int tw, int th);
+bool wants_gather(const ImageJob &j, int op);
+bool tiled_supported(int c, kr_dtype st);
 
 }  // namespace kr

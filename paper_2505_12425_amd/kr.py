@@ -183,3 +183,80 @@ def hbm_copy(dst, src, nbytes: int | None = None, stream=None) -> None:
     """kr_hbm_copy between two device tensors (the bandwidth ceiling probe)."""
     n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     check(lib().kr_hbm_copy(dst.data_ptr(), src.data_ptr(), n, _stream(stream)))
+
+
+# ---------------------------------------------------------------- batches
+def _batch_items(specs):
+    """ctypes array of BatchItem from specs: dicts with keys op ("resize" or
+    "warp"), src, dst (tensors), and for warps m (2x3) and optional inverse."""
+    n = len(specs)
+    arr = (BatchItem * max(n, 1))()
+    c = st = dt = None
+    for i, sp in enumerate(specs):
+        sp_ = dict(sp)
+        sptr, sh, sw, sc, s_t = _image(sp_["src"])
+        dptr, dh, dw, dc, d_t = _image(sp_["dst"])
+        if sc != dc or (c is not None and (sc != c or s_t != st or d_t != dt)):
+            raise ValueError("batch items must share channel count and dtypes")
+        c, st, dt = sc, s_t, d_t
+        it = arr[i]
+        it.op = OP_WARP if sp_.get("op", "resize") == "warp" else OP_RESIZE
+        it.src, it.src_h, it.src_w = sptr, sh, sw
+        it.dst, it.dst_h, it.dst_w = dptr, dh, dw
+        if it.op == OP_WARP:
+            vals = [float(v) for v in (sp_["m"].reshape(-1).tolist() if hasattr(sp_["m"], "reshape") else sp_["m"])]
+            for k in range(6):
+                it.m[k] = vals[k]
+            it.flags = WARP_INVERSE_MAP if sp_.get("inverse", False) else 0
+        else:
+            for k in range(6):
+                it.m[k] = 0.0
+            it.flags = 0
+    return arr, n, c, st, dt
+
+
+def batch_workspace_size(n: int) -> int:
+    return int(lib().kr_resize_batch_workspace_size(n))
+
+
+def resize_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None, workspace=None,
+                 stream=None) -> None:
+    """kr_resize_batch: every item of `specs` in one launch per operation.
+    `workspace` is a device tensor of at least batch_workspace_size(n) bytes
+    (allocated here if None)."""
+    import torch
+    arr, n, c, st, dt = _batch_items(specs)
+    if n == 0:
+        return
+    need = batch_workspace_size(n)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    check(lib().kr_resize_batch(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
+                                workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+class BatchPlan:
+    """kr_batch_plan_*: a validated work-list captured in a HIP graph; launch()
+    replays it.  The tensors named by the specs must outlive the plan."""
+
+    def __init__(self, specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None):
+        arr, n, c, st, dt = _batch_items(specs)
+        self._keep = [sp["src"] for sp in specs] + [sp["dst"] for sp in specs]
+        h = ctypes.c_void_p()
+        check(lib().kr_batch_plan_create(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
+                                         ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        check(lib().kr_batch_plan_launch(self._h, _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().kr_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

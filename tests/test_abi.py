@@ -139,3 +139,42 @@ def test_copy_probe_validation():
     assert L.kr_hbm_copy(B, A + 3, 16, None) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_hbm_copy(A + 16, A, 64, None) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_hbm_copy(B, A, 0, None) == kr.OK  # nothing to do, nothing enqueued
+
+
+def batch_items(n=2, op=0, dst_stride=4096):
+    arr = (kr.BatchItem * n)()
+    for i in range(n):
+        arr[i].op = op
+        arr[i].src, arr[i].src_h, arr[i].src_w = A, 100, 100
+        arr[i].dst, arr[i].dst_h, arr[i].dst_w = B + i * dst_stride, 10, 10
+    return arr
+
+
+def test_batch_validation():
+    L = kr.lib()
+    ws = A + 0x10000000
+    assert L.kr_resize_batch(batch_items(dst_stride=0), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, None) \
+        == kr.ERR_INVALID_ARGUMENT  # overlapping destinations
+    assert L.kr_resize_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 16, None) == kr.ERR_WORKSPACE_TOO_SMALL
+    assert L.kr_resize_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws + 8, 1 << 20, None) \
+        == kr.ERR_INVALID_ARGUMENT  # misaligned workspace
+    assert L.kr_resize_batch(batch_items(op=7), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, None) \
+        == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_resize_batch(batch_items(), 2, 1, 0, 0, 1, 0.0, None, ws, 1 << 20, None) == kr.ERR_UNSUPPORTED
+    assert L.kr_resize_batch(batch_items(), 2, 3, 1, 1, 1, 0.0, None, ws, 1 << 20, None) == kr.ERR_UNSUPPORTED
+    assert L.kr_resize_batch(None, 0, 3, 0, 0, 1, 0.0, None, None, 0, None) == kr.OK
+    arr = batch_items(op=1)
+    for k, v in enumerate([1, 2, 0, 2, 4, 0]):  # singular warp matrix
+        arr[0].m[k] = v
+    assert L.kr_resize_batch(arr, 2, 3, 0, 0, 0, 0.0, None, ws, 1 << 20, None) == kr.ERR_SINGULAR_MATRIX
+    # a destination inside a source
+    arr = batch_items()
+    arr[1].dst = A + 64
+    assert L.kr_resize_batch(arr, 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, None) == kr.ERR_INVALID_ARGUMENT
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.kr_batch_plan_create(batch_items(op=7), 2, 3, 0, 0, 1, 0.0, None, ctypes.byref(h)) \
+        == kr.ERR_INVALID_ARGUMENT
+    assert h.value is None
+    assert L.kr_batch_plan_launch(None, None) == kr.ERR_INVALID_ARGUMENT
+    L.kr_batch_plan_destroy(None)

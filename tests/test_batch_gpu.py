@@ -1,0 +1,131 @@
+"""GPU parity of the batched forms (one launch per operation over a work-list
+of output tiles, and its graph-captured plan) through the C ABI.
+
+Every item must equal the oracle (u8 bit-exact, f32 within 1e-3 on the 0..255
+scale) and equal the single-image call on the same item bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_12425_amd import workloads as wl
+from tests.gpu_util import assert_f32_close, assert_u8_equal, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_12425_amd import kr  # noqa: E402
+
+MEAN, STD = wl.IMAGENET_MEAN, wl.IMAGENET_STD
+TH = 16
+
+
+def _single(spec, **kw):
+    d = torch.empty_like(spec["dst"])
+    if spec["op"] == "warp":
+        kr.warp_affine(spec["src"], d, spec["m"], **kw)
+    else:
+        kr.resize(spec["src"], d, **kw)
+    return d
+
+
+def test_batch_256_mixed_sizes_to_224_normalized():
+    shapes = wl.batch_shapes(256, 240, 2160, seed=0)
+    say(f"batch resize 256 images -> 224x224 f32 normalized (first {shapes[:3]})")
+    imgs = [wl.uniform_u8(h, w, 3, seed=i) for i, (h, w) in enumerate(shapes)]
+    specs = [{"op": "resize", "src": torch.from_numpy(im).cuda(),
+              "dst": torch.empty((224, 224, 3), dtype=torch.float32, device="cuda")} for im in imgs]
+    kr.resize_batch(specs, border=kr.REPLICATE, mean=MEAN, std=STD)
+    torch.cuda.synchronize()
+    for i, (im, sp) in enumerate(zip(imgs, specs)):
+        got = sp["dst"].cpu().numpy()
+        exp = oracle.resize(im, 224, 224, "f64", oracle.REPLICATE, 0, MEAN, STD, threads=TH)
+        assert_f32_close(got, exp, f"item {i} {im.shape}", std=STD)
+        single = _single(sp, border=kr.REPLICATE, mean=MEAN, std=STD)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy(), got), f"item {i}: batch != single"
+
+
+def test_batch_64_warps_1080p_u8():
+    rng = np.random.default_rng(3)
+    say("batch warp 64 x 1080p u8")
+    imgs, specs = [], []
+    for i in range(64):
+        im = wl.uniform_u8(1080, 1920, 3, seed=100 + i)
+        m = wl.random_affine_batch(1080, 1920, rng)
+        imgs.append((im, m))
+        specs.append({"op": "warp", "src": torch.from_numpy(im).cuda(), "m": m,
+                      "dst": torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda")})
+    kr.resize_batch(specs, border=kr.CONSTANT, border_value=0)
+    torch.cuda.synchronize()
+    for i, ((im, m), sp) in enumerate(zip(imgs, specs)):
+        got = sp["dst"].cpu().numpy()
+        if i % 4 == 0:  # the oracle on every fourth image, all compared with the single call
+            assert_u8_equal(got, oracle.warp(im, m, 1080, 1920, "u8", threads=TH), f"warp item {i}")
+        single = _single(sp, border=kr.CONSTANT)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy(), got), f"item {i}: batch != single"
+
+
+@pytest.mark.parametrize("c,out", [(3, "u8"), (3, "f32"), (4, "u8")])
+def test_mixed_batch_and_plan_replays(c, out):
+    rng = np.random.default_rng(7 + c)
+    dt = torch.uint8 if out == "u8" else torch.float32
+    say(f"mixed batch c={c} out={out}")
+    specs, refs = [], []
+    for i in range(24):
+        h, w = int(rng.integers(20, 700)), int(rng.integers(20, 700))
+        im = wl.uniform_u8(h, w, c, seed=300 + i)
+        dh, dw = int(rng.integers(8, 500)), int(rng.integers(8, 500))
+        if i % 3 == 0:
+            m = wl.affine_compose(h, w, rng.uniform(-60, 60), rng.uniform(0.3, 2.0), rng.uniform(-0.3, 0.3),
+                                  rng.uniform(-50, 50), rng.uniform(-50, 50))
+            spec = {"op": "warp", "src": torch.from_numpy(im).cuda(), "m": m,
+                    "dst": torch.empty((dh, dw, c), dtype=dt, device="cuda")}
+            ref = oracle.warp(im, m, dh, dw, "u8" if out == "u8" else "f64", False, oracle.REPLICATE, 0)
+        else:
+            spec = {"op": "resize", "src": torch.from_numpy(im).cuda(),
+                    "dst": torch.empty((dh, dw, c), dtype=dt, device="cuda")}
+            ref = oracle.resize(im, dh, dw, "u8" if out == "u8" else "f64", oracle.REPLICATE, 0)
+        specs.append(spec)
+        refs.append(ref)
+
+    def check_all(tag):
+        for i, (sp, ref) in enumerate(zip(specs, refs)):
+            got = sp["dst"].cpu().numpy()
+            if out == "u8":
+                assert_u8_equal(got, ref, f"{tag} item {i}")
+            else:
+                assert_f32_close(got, ref, f"{tag} item {i}")
+
+    kr.resize_batch(specs, border=kr.REPLICATE)
+    torch.cuda.synchronize()
+    check_all("batch")
+    eager = [sp["dst"].clone() for sp in specs]
+    plan = kr.BatchPlan(specs, border=kr.REPLICATE)
+    try:
+        for rep in range(3):
+            for sp in specs:
+                sp["dst"].zero_()
+            scratch = torch.randn(1 << 20, device="cuda")  # unrelated eager work between replays
+            scratch.mul_(2.0)
+            plan.launch()
+            torch.cuda.synchronize()
+            for i, sp in enumerate(specs):
+                assert torch.equal(sp["dst"], eager[i]), f"replay {rep} item {i} differs from eager"
+    finally:
+        plan.close()
+
+
+def test_batch_single_item_and_empty():
+    im = wl.uniform_u8(37, 53, 3, seed=9)
+    src = torch.from_numpy(im).cuda()
+    dst = torch.empty((19, 77, 3), dtype=torch.uint8, device="cuda")
+    kr.resize_batch([{"op": "resize", "src": src, "dst": dst}])
+    torch.cuda.synchronize()
+    assert_u8_equal(dst.cpu().numpy(), oracle.resize(im, 19, 77, "u8"), "single-item batch")
+    kr.resize_batch([])  # nothing to do
