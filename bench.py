@@ -242,15 +242,183 @@ def bench_4k(args, torch, kr, wl):
     }
 
 
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v, np.float64), q))
+
+
+def _time_loop(torch, fn, reps):
+    """Per-call durations (ms) of fn() with an event pair around each call."""
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        out.append((a, b))
+    torch.cuda.synchronize()
+    return [x.elapsed_time(y) for x, y in out]
+
+
+# ---------------------------------------------------------------- batched resize
+def bench_batch(args, torch, kr, wl):
+    """256 images, H, W uniform in [240, 2160] -> 224x224 f32, per-channel
+    normalised; per-image launches vs one batched launch vs a graph plan."""
+    shapes = wl.batch_shapes(256, 240, 2160, seed=0)
+    srcs = [torch.from_numpy(wl.uniform_u8(h, w, 3, seed=i)).cuda() for i, (h, w) in enumerate(shapes)]
+    dsts = [torch.empty((224, 224, 3), dtype=torch.float32, device="cuda") for _ in shapes]
+    mean, std = wl.IMAGENET_MEAN, wl.IMAGENET_STD
+    specs = [{"op": "resize", "src": s, "dst": d} for s, d in zip(srcs, dsts)]
+    ws = torch.empty(kr.batch_workspace_size(len(specs)), dtype=torch.uint8, device="cuda")
+    plan = kr.BatchPlan(specs, border=kr.REPLICATE, mean=mean, std=std)
+
+    def per_image():
+        for s, d in zip(srcs, dsts):
+            kr.resize(s, d, border=kr.REPLICATE, mean=mean, std=std)
+
+    def batched():
+        kr.resize_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws)
+
+    for f in (per_image, batched, plan.launch):
+        for _ in range(args.warmup):
+            f()
+    torch.cuda.synchronize()
+    reps = max(args.steps, 200)
+    t_img = _time_loop(torch, per_image, max(args.steps, 20))
+    t_bat = _time_loop(torch, batched, reps)
+    t_plan = _time_loop(torch, plan.launch, reps)
+    plan.close()
+    touched = sum(resize_touched_bytes(h, w, 224, 224) for h, w in shapes)
+    alg = touched + 256 * 224 * 224 * 12
+    px = 256 * 224 * 224
+    ms = float(np.median(t_plan))
+    gbps = alg / (ms * 1e-3) / 1e9
+    return {
+        "metric": "output Gpixels/s (256 mixed-size images -> 224x224 f32 normalised, one graph-replayed batch)",
+        "value": round(px / (ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(ms, 4),
+        "config": {"workload": "batch: 256 RGB u8 images, H and W uniform in [240, 2160] (seed 0), bilinear "
+                               "to 224x224, u8 -> f32 with ImageNet mean/std, REPLICATE border",
+                   "px_per_step": px, "alg_bytes": alg},
+        "roofline": {"bound": "hbm", "kernel": "batch_resize_f32", "achieved": round(gbps, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": _traffic_from_profiles("batch_resize_f32"), "alg_bytes_per_launch": alg,
+                     "avg_launch_us": round(ms * 1e3, 3)},
+        "per_image_ms": round(float(np.median(t_img)), 4), "batched_ms": round(float(np.median(t_bat)), 4),
+        "plan_ms": round(ms, 4), "speedup_vs_per_image": round(float(np.median(t_img)) / ms, 2),
+        "plan_p50_ms": round(_pct(t_plan, 50), 4), "plan_p99_ms": round(_pct(t_plan, 99), 4),
+        "per_image_p99_ms": round(_pct(t_img, 99), 4),
+    }
+
+
+# ---------------------------------------------------------------- batched warp
+def bench_warpbatch(args, torch, kr, wl):
+    """64 warps of 1920x1080x3 u8 images, each with its own random affine,
+    constant-0 border, u8 output; graph-replayed batch vs per-image launches."""
+    rng = np.random.default_rng(0)
+    srcs, mats = [], []
+    for i in range(64):
+        srcs.append(torch.from_numpy(wl.uniform_u8(1080, 1920, 3, seed=100 + i)).cuda())
+        mats.append(wl.random_affine_batch(1080, 1920, rng))
+    dsts = [torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda") for _ in srcs]
+    specs = [{"op": "warp", "src": s, "dst": d, "m": m} for s, d, m in zip(srcs, dsts, mats)]
+    plan = kr.BatchPlan(specs, border=kr.CONSTANT)
+
+    def per_image():
+        for s, d, m in zip(srcs, dsts, mats):
+            kr.warp_affine(s, d, m, border=kr.CONSTANT)
+
+    for f in (per_image, plan.launch):
+        for _ in range(args.warmup):
+            f()
+    torch.cuda.synchronize()
+    t_img = _time_loop(torch, per_image, max(args.steps, 20))
+    t_plan = _time_loop(torch, plan.launch, max(args.steps, 200))
+    plan.close()
+    touched = sum(warp_touched_bytes(1080, 1920, 1080, 1920, kr.invert_affine(m.reshape(6))) for m in mats)
+    alg = touched + 64 * 1080 * 1920 * 3
+    px = 64 * 1080 * 1920
+    ms = float(np.median(t_plan))
+    gbps = alg / (ms * 1e-3) / 1e9
+    return {
+        "metric": "output Gpixels/s (64 x 1080p affine warps, one graph-replayed batch)",
+        "value": round(px / (ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(ms, 4),
+        "config": {"workload": "warpbatch: 64 RGB u8 1920x1080 images, rotation U[-45,45] deg, scale U[0.5,1.5], "
+                               "shear U[-0.2,0.2], translation +-10%, constant-0 border, u8 out",
+                   "px_per_step": px, "alg_bytes": alg},
+        "roofline": {"bound": "hbm", "kernel": "batch_warp_u8", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": _traffic_from_profiles("batch_warp_u8"), "alg_bytes_per_launch": alg,
+                     "avg_launch_us": round(ms * 1e3, 3)},
+        "per_image_ms": round(float(np.median(t_img)), 4), "plan_ms": round(ms, 4),
+        "speedup_vs_per_image": round(float(np.median(t_img)) / ms, 2),
+        "plan_p50_ms": round(_pct(t_plan, 50), 4), "plan_p99_ms": round(_pct(t_plan, 99), 4),
+    }
+
+
+# ---------------------------------------------------------------- serving
+def bench_serve(args, torch, kr, wl):
+    """10,000 requests (70 % resize, 30 % warp) with Poisson arrivals, sources
+    resident in HBM (windows into one seeded buffer), outputs in a budgeted
+    arena; continuous batching vs a per-request FIFO at the same QPS."""
+    n = args.requests
+    pool_bytes = 1 << 30
+    pool = torch.from_numpy(wl.uniform_u8(1, pool_bytes, 1, seed=1).reshape(-1)).cuda()
+    base = pool.data_ptr()
+    reqs = wl.serving_requests(n, qps=1.0, seed=0)
+    rng = np.random.default_rng(2)
+    krs, out_px = [], 0
+    for r in reqs:
+        nbytes = r.src_h * r.src_w * 3
+        off = int(rng.integers(0, (pool_bytes - nbytes) // 256)) * 256
+        krs.append(kr.make_request("warp" if r.op else "resize", (base + off, r.src_h, r.src_w), r.dst_h, r.dst_w,
+                                   np.array(r.m) if r.op else None))
+        out_px += r.dst_h * r.dst_w
+    unit_gaps = np.diff([0.0] + [r.arrival_s for r in reqs])  # Poisson at 1 request/s
+
+    def run(qps, slots, batch, budget):
+        srv = kr.Server(budget, slots=slots, max_batch=batch, c=3, out="u8", border=kr.REPLICATE)
+        arr = np.cumsum(unit_gaps / qps) if qps else np.zeros(n)
+        t0 = time.perf_counter()
+        lat = np.asarray(srv.run_trace(krs, arr))
+        wall = time.perf_counter() - t0
+        srv.close()
+        return {"qps": round(qps, 1) if qps else "saturation", "p50_ms": round(_pct(lat, 50) * 1e3, 3),
+                "p99_ms": round(_pct(lat, 99) * 1e3, 3), "Gpix_s": round(out_px / wall / 1e9, 3),
+                "req_s": round(n / wall, 1), "wall_s": round(wall, 3)}
+
+    budget = args.budget_mb << 20
+    sat = run(0, 4, 64, budget)
+    sat_fifo = run(0, 1, 1, budget)
+    sweep = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        q = frac * sat["req_s"]
+        sweep.append({"frac_of_saturation": frac, "batched": run(q, 4, 64, budget), "fifo": run(q, 1, 1, budget)})
+    head = max((s for s in sweep if s["batched"]["p99_ms"] <= args.slo_ms), key=lambda s: s["frac_of_saturation"],
+               default=sweep[0])
+    return {
+        "metric": "served output Gpixels/s at the highest swept QPS meeting the p99 SLO (continuous batching)",
+        "value": head["batched"]["Gpix_s"], "unit": "Gpix/s", "ms_per_step": None,
+        "config": {"workload": f"serve: {n} requests, Poisson arrivals, 70% resize / 30% warp, source pixel count "
+                               "log-uniform [0.1, 8] MP, aspect log-uniform [0.5, 2], targets {224,384,512,1024}^2, "
+                               "u8 out, sources resident in HBM",
+                   "budget_mb": args.budget_mb, "slots": 4, "max_batch": 64, "slo_p99_ms": args.slo_ms},
+        "saturation": {"batched": sat, "fifo": sat_fifo,
+                       "speedup_vs_fifo": round(sat["req_s"] / max(sat_fifo["req_s"], 1e-9), 2)},
+        "sweep": sweep, "headline": head,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="4k", choices=["4k"])
+    ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve"])
     ap.add_argument("--cold-copies", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--budget-mb", type=int, default=2048)
+    ap.add_argument("--slo-ms", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the operators shard per image "
@@ -263,6 +431,18 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     kr.lib()
+    common = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    if args.workload != "4k":
+        fn = {"batch": bench_batch, "warpbatch": bench_warpbatch, "serve": bench_serve}[args.workload]
+        r = fn(args, torch, kr, wl)
+        out = {"metric": r.pop("metric"), "value": r.pop("value"), "unit": r.pop("unit")}
+        out.update(common)
+        out["ms_per_step"] = r.pop("ms_per_step")
+        out["dtype"] = "u8 fixed-point / f32"
+        out.update(r)
+        print(json.dumps(out))
+        return
     copy_gbps = _hbm_copy_ceiling(torch, kr)
     r = bench_4k(args, torch, kr, wl)
     dom = r["dominant"]

@@ -121,14 +121,16 @@ typedef struct {
 size_t kr_resize_batch_workspace_size(int n);
 
 /*
- * Many resizes and warps of uneven sizes in ONE persistent launch over a
- * work-list of output tiles (the batched form of the operators above).
+ * Many resizes and warps of uneven sizes in one launch per operation (all
+ * resizes in one, all warps in another) over a work-list of output tiles
+ * spanning every image (the batched form of the operators above).
  * items: HOST array of n items, all with c channels and types (src_t, dst_t);
  * border, border_value and norm apply to every item.  workspace: DEVICE
  * buffer of at least kr_resize_batch_workspace_size(n) bytes, owned by the
  * caller and not touched by other work until the batch completes.  Each
  * item's output is bit-identical to the single-image call on the same item.
- * Destinations must not overlap each other or any source.
+ * Destinations must not overlap each other or any source.  Batched launches
+ * take u8 sources with 3 or 4 channels (KR_ERR_UNSUPPORTED otherwise).
  */
 kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
                           kr_border border, float border_value, const kr_normalize *norm,
@@ -137,7 +139,7 @@ kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src
 /*
  * A reusable batch: kr_batch_plan_create validates the items, builds the
  * work-list once (it allocates and fills its own device memory, synchronously)
- * and captures {counter reset, persistent kernel} into a HIP graph.
+ * and captures the batch's launches into a HIP graph (kernel nodes only).
  * kr_batch_plan_launch replays that graph on stream.  Source and destination
  * buffers named by the items must stay valid while the plan is used.
  * kr_batch_plan_destroy frees the plan (after synchronising its last launch);
@@ -157,6 +159,70 @@ void kr_batch_plan_destroy(kr_batch_plan *plan);
  * F = -(D*c + E*f).  Same singularity rule as kr_warp_affine.
  */
 kr_status kr_invert_affine(const double m[6], double inv[6]);
+
+/*
+ * Request server: continuous batching of resize / warp requests on one GPU.
+ *
+ * Requests wait in a FIFO queue.  Whenever one of `slots` in-flight batch
+ * slots (one HIP stream each) is free, queued requests are admitted in
+ * arrival order into a new batch while their outputs fit in the output arena
+ * (budget_bytes of device memory, allocated once by kr_server_create) and the
+ * batch holds fewer than max_batch requests; the batch is launched at once
+ * (a work-list launch as in kr_resize_batch) and batches of different slots
+ * run concurrently.  Every output is bit-identical to the single-image call.
+ * Outputs stay in the arena until kr_server_release().  Sources are caller
+ * owned device images that must stay valid until their request completes.
+ * A server is driven by one host thread at a time (calls on one server must
+ * not overlap); different servers are independent.  Supported: u8 sources
+ * with 3 or 4 channels, u8 or f32 outputs.
+ */
+typedef struct kr_server kr_server;
+
+typedef struct {
+    size_t budget_bytes; /* output arena size (>= 256) */
+    int slots;           /* batches in flight, 1..16 */
+    int max_batch;       /* requests per batch, 1..4096 */
+} kr_server_config;
+
+/* One request; op 0 = resize, 1 = warp (m, flags as in kr_warp_affine). */
+typedef struct {
+    int op;
+    const void *src;
+    int src_h, src_w;
+    int dst_h, dst_w;
+    double m[6];
+    int flags;
+} kr_request;
+
+typedef struct {
+    uint64_t id;      /* as returned by kr_server_submit */
+    void *dst;        /* device pointer to the output (dst_h x dst_w x c) in the arena */
+    size_t dst_bytes;
+    double t_done;    /* server clock (seconds) when the completion was observed */
+} kr_completion;
+
+kr_status kr_server_create(const kr_server_config *cfg, int c, kr_dtype src_t, kr_dtype dst_t, kr_border border,
+                           float border_value, const kr_normalize *norm, kr_server **server);
+/* Seconds since the server was created (the clock of t_done). */
+double kr_server_now(const kr_server *server);
+/* Queue one request.  KR_ERR_OUT_OF_BUDGET if its output can never fit. */
+kr_status kr_server_submit(kr_server *server, const kr_request *req, uint64_t *id);
+/* Make progress (harvest finished batches, admit and launch new ones) and
+ * return up to max_out completions (*n_out of them). */
+kr_status kr_server_poll(kr_server *server, kr_completion *out, int max_out, int *n_out);
+/* Free a completed request's output block. */
+kr_status kr_server_release(kr_server *server, uint64_t id);
+kr_status kr_server_stats(const kr_server *server, size_t *arena_used, size_t *queued, int *busy_slots);
+/*
+ * Replay a request trace on the host clock: request i is submitted when
+ * arrival_s[i] seconds (ascending) have passed since the call started; every
+ * output is released as soon as it completes.  latency_s[i] = completion
+ * observed - arrival_s[i].  Needs an idle server with nothing unreleased.
+ */
+kr_status kr_server_run_trace(kr_server *server, const kr_request *reqs, const double *arrival_s, int n,
+                              double *latency_s);
+/* Waits for in-flight work, then frees everything; NULL is ignored. */
+void kr_server_destroy(kr_server *server);
 
 /* Static text for a status code. */
 const char *kr_status_string(kr_status s);

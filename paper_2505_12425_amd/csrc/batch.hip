@@ -14,9 +14,8 @@
 #include <new>
 #include <vector>
 
+#include "batch_internal.h"
 #include "kr_api_internal.h"
-#include "tiled.h"
-#include "tiled_launch.h"
 
 namespace kr {
 
@@ -43,17 +42,6 @@ __global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict
         return true;
     });
 }
-
-// One operation group of a batch, ready to launch.
-struct BatchGroup {
-    int op = OP_RESIZE;
-    TileCfg cfg{4, 16, 1, 1, false};
-    TileGeom G{0, 0};
-    int njobs = 0;
-    int ntiles = 0;
-    size_t lds = 0;
-    const TiledJob *jobs_dev = nullptr;  // device copy of the job table
-};
 
 template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
 static hipError_t launch_group_cfg(const BatchGroup &g, const Epilogue &e, hipStream_t s)
@@ -89,7 +77,7 @@ static hipError_t launch_group_c(const BatchGroup &g, const Epilogue &e, hipStre
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue &e, hipStream_t s)
+hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue &e, hipStream_t s)
 {
     if (g.njobs == 0)
         return hipSuccess;
@@ -118,8 +106,7 @@ constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's w
 // Build the host-side job table of one operation group.  Items whose own box
 // would exceed the LDS budget (and large-ratio resizes) run every tile on the
 // global-gather path; the others set the launch-wide LDS geometry.
-static void build_group(int op, bool f32, const std::vector<ImageJob> &imgs, BatchGroup &g,
-                        std::vector<TiledJob> &table)
+void build_group(int op, bool f32, const std::vector<ImageJob> &imgs, BatchGroup &g, std::vector<TiledJob> &table)
 {
     g.op = op;
     g.cfg = batch_cfg(op, f32);
@@ -211,7 +198,7 @@ static kr_status check_items(const kr_batch_item *items, int n, int c, kr_dtype 
 
 // Device layout of a batch workspace: the resize group's job table, then the
 // warp group's, each 256-byte aligned.
-static size_t table_bytes(int n) { return ((size_t)n * sizeof(TiledJob) + 255) & ~(size_t)255; }
+size_t kr::table_bytes(int n) { return ((size_t)n * sizeof(TiledJob) + 255) & ~(size_t)255; }
 
 extern "C" {
 

@@ -260,3 +260,118 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- request server
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int), ("max_batch", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("src", ctypes.c_void_p), ("src_h", ctypes.c_int), ("src_w", ctypes.c_int),
+                ("dst_h", ctypes.c_int), ("dst_w", ctypes.c_int), ("m", ctypes.c_double * 6), ("flags", ctypes.c_int)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("dst", ctypes.c_void_p), ("dst_bytes", ctypes.c_size_t),
+                ("t_done", ctypes.c_double)]
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_decl", False):
+        vp, i, f, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+        L.kr_server_create.argtypes = [ctypes.POINTER(ServerConfig), i, i, i, i, f, ctypes.POINTER(Normalize),
+                                       ctypes.POINTER(vp)]
+        L.kr_server_create.restype = i
+        L.kr_server_now.argtypes = [vp]
+        L.kr_server_now.restype = d
+        L.kr_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.kr_server_submit.restype = i
+        L.kr_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i, ctypes.POINTER(i)]
+        L.kr_server_poll.restype = i
+        L.kr_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.kr_server_release.restype = i
+        L.kr_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(i)]
+        L.kr_server_stats.restype = i
+        L.kr_server_run_trace.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(d), i, ctypes.POINTER(d)]
+        L.kr_server_run_trace.restype = i
+        L.kr_server_destroy.argtypes = [vp]
+        L.kr_server_destroy.restype = None
+        L._server_decl = True
+    return L
+
+
+def make_request(op: str, src, dst_h: int, dst_w: int, m=None, inverse: bool = False) -> Request:
+    """A kr_request for a resident source tensor (or (ptr, h, w) tuple)."""
+    r = Request()
+    if isinstance(src, tuple):
+        r.src, r.src_h, r.src_w = src
+    else:
+        sp, sh, sw, _, _ = _image(src)
+        r.src, r.src_h, r.src_w = sp, sh, sw
+    r.op = OP_WARP if op == "warp" else OP_RESIZE
+    r.dst_h, r.dst_w = dst_h, dst_w
+    if r.op == OP_WARP:
+        vals = [float(v) for v in (m.reshape(-1).tolist() if hasattr(m, "reshape") else m)]
+        for k in range(6):
+            r.m[k] = vals[k]
+        r.flags = WARP_INVERSE_MAP if inverse else 0
+    return r
+
+
+class Server:
+    """kr_server_*: continuous batching of resize/warp requests with outputs in
+    a device arena of `budget_bytes`."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4, max_batch: int = 64, c: int = 3, out: str = "u8",
+                 border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None):
+        L = _server_lib()
+        cfg = ServerConfig(budget_bytes, slots, max_batch)
+        h = ctypes.c_void_p()
+        self.c, self.out = c, out
+        check(L.kr_server_create(ctypes.byref(cfg), c, U8, U8 if out == "u8" else F32, border, float(border_value),
+                                 _normalize(mean, std, c), ctypes.byref(h)))
+        self._h = h
+
+    def now(self) -> float:
+        return _server_lib().kr_server_now(self._h)
+
+    def submit(self, req: Request) -> int:
+        rid = ctypes.c_uint64()
+        check(_server_lib().kr_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, max_out: int = 256):
+        buf = (Completion * max_out)()
+        n = ctypes.c_int()
+        check(_server_lib().kr_server_poll(self._h, buf, max_out, ctypes.byref(n)))
+        return [(buf[k].id, buf[k].dst, buf[k].dst_bytes, buf[k].t_done) for k in range(n.value)]
+
+    def release(self, rid: int) -> None:
+        check(_server_lib().kr_server_release(self._h, rid))
+
+    def stats(self):
+        used, queued, busy = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()
+        check(_server_lib().kr_server_stats(self._h, ctypes.byref(used), ctypes.byref(queued), ctypes.byref(busy)))
+        return used.value, queued.value, busy.value
+
+    def run_trace(self, reqs, arrivals):
+        n = len(reqs)
+        arr = (Request * max(n, 1))(*reqs)
+        t = (ctypes.c_double * max(n, 1))(*[float(a) for a in arrivals])
+        lat = (ctypes.c_double * max(n, 1))()
+        check(_server_lib().kr_server_run_trace(self._h, arr, t, n, lat))
+        return [lat[k] for k in range(n)]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _server_lib().kr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

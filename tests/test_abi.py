@@ -178,3 +178,24 @@ def test_batch_validation():
     assert h.value is None
     assert L.kr_batch_plan_launch(None, None) == kr.ERR_INVALID_ARGUMENT
     L.kr_batch_plan_destroy(None)
+
+
+def test_server_config_validation():
+    L = kr._server_lib()
+    h = ctypes.c_void_p()
+    bad = [kr.ServerConfig(0, 1, 1), kr.ServerConfig(1 << 20, 0, 1), kr.ServerConfig(1 << 20, 17, 1),
+           kr.ServerConfig(1 << 20, 1, 0), kr.ServerConfig(1 << 20, 1, 5000)]
+    for cfg in bad:
+        assert L.kr_server_create(ctypes.byref(cfg), 3, kr.U8, kr.U8, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
+            == kr.ERR_INVALID_ARGUMENT
+    ok = kr.ServerConfig(1 << 20, 2, 8)
+    assert L.kr_server_create(ctypes.byref(ok), 1, kr.U8, kr.U8, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
+        == kr.ERR_UNSUPPORTED
+    assert L.kr_server_create(ctypes.byref(ok), 3, kr.F32, kr.F32, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
+        == kr.ERR_UNSUPPORTED
+    assert L.kr_server_create(ctypes.byref(ok), 3, kr.U8, kr.U8, kr.REPLICATE, 300.0, None, ctypes.byref(h)) \
+        == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_server_create(None, 3, kr.U8, kr.U8, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
+        == kr.ERR_INVALID_ARGUMENT
+    assert h.value is None
+    L.kr_server_destroy(None)
