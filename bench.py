@@ -189,6 +189,14 @@ def bench_4k(args, torch, kr, wl):
     px = {"resize_u8": 1080 * 1920, "resize_f32": 1080 * 1920, "warp_u8": h * w, "warp_f32": h * w}
     px_per_step = sum(px.values())
 
+    tuned = {}
+    if args.autotune:
+        for n in names:
+            d = outs[n]
+            if n.startswith("resize"):
+                tuned[n] = kr.autotune_image("resize", srcs[0], d, border=kr.REPLICATE, reps=20)
+            else:
+                tuned[n] = kr.autotune_image("warp", srcs[0], d, m, border=kr.CONSTANT, reps=20)
     for i in range(args.warmup):
         for n in names:
             launch(n, srcs[i % copies])
@@ -238,7 +246,7 @@ def bench_4k(args, torch, kr, wl):
         "config": {"workload": "4k: 3840x2160x3 u8 -> resize 1920x1080 + warp_affine 3840x2160 "
                                "(seed-0 rotation/scale/translation, constant-0 border), u8 and f32 outputs",
                    "src": "3840x2160x3 u8", "cold_copies": copies, "px_per_step": px_per_step},
-        "dominant": dom, "kernels": kern, "cpu_args": (img, m),
+        "dominant": dom, "kernels": kern, "cpu_args": (img, m), "autotune": tuned,
     }
 
 
@@ -269,6 +277,8 @@ def bench_batch(args, torch, kr, wl):
     mean, std = wl.IMAGENET_MEAN, wl.IMAGENET_STD
     specs = [{"op": "resize", "src": s, "dst": d} for s, d in zip(srcs, dsts)]
     ws = torch.empty(kr.batch_workspace_size(len(specs)), dtype=torch.uint8, device="cuda")
+    tuned = (kr.autotune_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws, reps=10)
+             if args.autotune else "")
     plan = kr.BatchPlan(specs, border=kr.REPLICATE, mean=mean, std=std)
 
     def per_image():
@@ -305,7 +315,7 @@ def bench_batch(args, torch, kr, wl):
         "per_image_ms": round(float(np.median(t_img)), 4), "batched_ms": round(float(np.median(t_bat)), 4),
         "plan_ms": round(ms, 4), "speedup_vs_per_image": round(float(np.median(t_img)) / ms, 2),
         "plan_p50_ms": round(_pct(t_plan, 50), 4), "plan_p99_ms": round(_pct(t_plan, 99), 4),
-        "per_image_p99_ms": round(_pct(t_img, 99), 4),
+        "per_image_p99_ms": round(_pct(t_img, 99), 4), "autotune": tuned,
     }
 
 
@@ -320,6 +330,7 @@ def bench_warpbatch(args, torch, kr, wl):
         mats.append(wl.random_affine_batch(1080, 1920, rng))
     dsts = [torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda") for _ in srcs]
     specs = [{"op": "warp", "src": s, "dst": d, "m": m} for s, d, m in zip(srcs, dsts, mats)]
+    tuned = kr.autotune_batch(specs, border=kr.CONSTANT, reps=10) if args.autotune else ""
     plan = kr.BatchPlan(specs, border=kr.CONSTANT)
 
     def per_image():
@@ -351,6 +362,7 @@ def bench_warpbatch(args, torch, kr, wl):
         "per_image_ms": round(float(np.median(t_img)), 4), "plan_ms": round(ms, 4),
         "speedup_vs_per_image": round(float(np.median(t_img)) / ms, 2),
         "plan_p50_ms": round(_pct(t_plan, 50), 4), "plan_p99_ms": round(_pct(t_plan, 99), 4),
+        "autotune": tuned,
     }
 
 
@@ -415,6 +427,8 @@ def main():
     ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve"])
     ap.add_argument("--cold-copies", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the built-in tile configurations instead of tuning them first")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--budget-mb", type=int, default=2048)
@@ -457,7 +471,7 @@ def main():
         "value": round(r["value"], 3), "unit": "Gpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8 fixed-point / f32", "data": "synthetic",
-        "config": r["config"], "roofline": roof, "kernels": r["kernels"],
+        "config": r["config"], "roofline": roof, "kernels": r["kernels"], "autotune": r["autotune"],
     }
     if not args.no_cpu_baseline:
         img, m = r["cpu_args"]

@@ -224,6 +224,43 @@ kr_status kr_server_run_trace(kr_server *server, const kr_request *reqs, const d
 /* Waits for in-flight work, then frees everything; NULL is ignored. */
 void kr_server_destroy(kr_server *server);
 
+/*
+ * Autotuner: picks the tile shape and pixels-per-thread of the u8-source
+ * kernels by timing every compiled configuration on the caller's own workload
+ * (the project-written tuner of the batched path).  The winner is recorded in
+ * a process-wide table keyed by (operation, channels, output type, single
+ * image or batch, half-octave class of source pixels per output pixel,
+ * factor-4 class of output pixels); later launches of the same class use it.
+ * Every configuration computes bit-identical results, so tuning changes
+ * speed only.  The table is loaded from the text file named by the
+ * environment variable KR_AUTOTUNE_CACHE on first use, if set.
+ *
+ * kr_autotune_image: same arguments as kr_resize_bilinear (op 0) or
+ * kr_warp_affine (op 1), plus reps timed launches per configuration (1..1000).
+ * It launches on stream, synchronises it, and leaves the correct output in
+ * dst.  report: NULL, or a host buffer receiving a one-line summary.
+ * Only u8 sources with 3 or 4 channels have configurations
+ * (KR_ERR_UNSUPPORTED otherwise).
+ * kr_autotune_batch: same arguments as kr_resize_batch plus reps and report;
+ * tunes the resize and the warp launch of the batch separately.
+ * kr_autotune_save: writes the table as text into buf (truncated to len
+ * bytes, NUL-terminated) and returns the bytes the full text needs.
+ * kr_autotune_load: merges a text table (as written by kr_autotune_save);
+ * a malformed line or an unknown configuration rejects the whole text
+ * (KR_ERR_INVALID_ARGUMENT, table unchanged).
+ * kr_autotune_clear: empties the table (launches return to the defaults).
+ */
+kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
+                            int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags, kr_border border,
+                            float border_value, const kr_normalize *norm, int reps, void *stream, char *report,
+                            size_t report_len);
+kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                            kr_border border, float border_value, const kr_normalize *norm, void *workspace,
+                            size_t workspace_bytes, int reps, void *stream, char *report, size_t report_len);
+size_t kr_autotune_save(char *buf, size_t len);
+kr_status kr_autotune_load(const char *text);
+void kr_autotune_clear(void);
+
 /* Static text for a status code. */
 const char *kr_status_string(kr_status s);
 

@@ -1,0 +1,111 @@
+// autotune.cpp -- the tuner's single-image entry point and the persistence of
+// the tuned table (kr_autotune_*).
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kr_api_internal.h"
+#include "tiled_launch.h"
+#include "tune.h"
+
+using namespace kr;
+
+extern "C" {
+
+kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
+                            int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags, kr_border border,
+                            float border_value, const kr_normalize *norm, int reps, void *stream, char *report,
+                            size_t report_len)
+{
+    clear_error();
+    if (op != KR_OP_RESIZE && op != KR_OP_WARP)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown op %d", op);
+    kr_status st = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    if (st != KR_OK)
+        return st;
+    if (!tiled_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "only u8 sources with 3 or 4 channels have tunable configurations");
+    if (reps < 1 || reps > 1000)
+        return fail(KR_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    if (op == KR_OP_WARP) {
+        if (flags & ~KR_WARP_INVERSE_MAP)
+            return fail(KR_ERR_INVALID_ARGUMENT, "unknown warp flags 0x%x", flags);
+        st = check_matrix(m, flags, j.inv);
+        if (st != KR_OK)
+            return st;
+    }
+    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a)
+            (void)hipEventDestroy(a);
+        return fail(KR_ERR_HIP, "event creation failed");
+    }
+    TileCfg best{};
+    float best_ms = -1;
+    kr_status result = KR_OK;
+    for (const TileCfg &cfg : image_candidates(op)) {
+        bool fits = false;
+        hipError_t err = launch_tiled_cfg(op, c, dst_t, cfg, j, e, s, fits);  // warm-up
+        if (err == hipSuccess && !fits)
+            continue;
+        if (err == hipSuccess)
+            err = hipEventRecord(a, s);
+        for (int r = 0; r < reps && err == hipSuccess; r++)
+            err = launch_tiled_cfg(op, c, dst_t, cfg, j, e, s, fits);
+        if (err == hipSuccess)
+            err = hipEventRecord(b, s);
+        if (err == hipSuccess)
+            err = hipEventSynchronize(b);
+        float ms = 0;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&ms, a, b);
+        if (err != hipSuccess) {
+            result = fail(KR_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(err));
+            break;
+        }
+        ms /= (float)reps;
+        if (best_ms < 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cfg;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (result != KR_OK)
+        return result;
+    if (best_ms < 0)
+        return KR_OK;  // no tiled configuration fits: launches keep the global-gather path
+    const TuneKey key = tune_key_image(op, c, dst_t == KR_F32, j);
+    tune_store(key, best);
+    if (report && report_len > 0)
+        std::snprintf(report, report_len, "%s -> %s (%.1f us)", tune_key_string(key).c_str(),
+                      tune_cfg_string(best).c_str(), best_ms * 1000.0f);
+    return KR_OK;
+}
+
+size_t kr_autotune_save(char *buf, size_t len)
+{
+    const std::string text = tune_dump();
+    if (buf && len > 0)
+        std::snprintf(buf, len, "%s", text.c_str());
+    return text.size() + 1;
+}
+
+kr_status kr_autotune_load(const char *text)
+{
+    clear_error();
+    if (!text)
+        return fail(KR_ERR_INVALID_ARGUMENT, "text is NULL");
+    if (!tune_load_text(text))
+        return fail(KR_ERR_INVALID_ARGUMENT, "malformed tuning table line");
+    return KR_OK;
+}
+
+void kr_autotune_clear(void) { tune_clear(); }
+
+}  // extern "C"

@@ -10,12 +10,15 @@
 // kr_resize_batch / kr_batch_plan_* (plans capture their launches in a HIP
 // graph; they record no memset nodes).
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <new>
 #include <vector>
 
 #include "batch_internal.h"
 #include "kr_api_internal.h"
+#include "tune.h"
 
 namespace kr {
 
@@ -58,10 +61,6 @@ static hipError_t launch_group_cfg(const BatchGroup &g, const Epilogue &e, hipSt
     return hipGetLastError();
 }
 
-// Batched tile configurations (PX, TXT, CPT, RPT).
-#define KR_BATCH_WARP_CFGS(X) X(4, 16, 1, 1) X(4, 16, 1, 2) X(1, 64, 1, 4) X(1, 64, 1, 8)
-#define KR_BATCH_RESIZE_CFGS(X) X(4, 16, 1, 1) X(1, 64, 1, 4) X(1, 64, 2, 4)
-
 template <int OP, int C, bool F32>
 static hipError_t launch_group_c(const BatchGroup &g, const Epilogue &e, hipStream_t s)
 {
@@ -92,24 +91,62 @@ hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue 
     return f ? launch_group_c<OP_RESIZE, 4, true>(g, e, s) : launch_group_c<OP_RESIZE, 4, false>(g, e, s);
 }
 
-// Tile shape of a batch group (small tiles: batches of small outputs still
-// produce many tiles; shrinking warps keep boxes small).
-static TileCfg batch_cfg(int op, bool f32)
+constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's widest box
+
+// Fraction of a group's output pixels whose images' boxes fit the LDS budget
+// under a configuration (the rest take the global-gather path).
+static double lds_coverage(int op, const TileCfg &cfg, const std::vector<ImageJob> &imgs)
 {
-    if (op == OP_WARP)
-        return f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false};
-    return f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false};
+    const int tw = cfg.txt * cfg.px * cfg.cpt, th = (KT_THREADS / cfg.txt) * cfg.rpt;
+    double tot = 0, fit = 0;
+    for (const ImageJob &j : imgs) {
+        const double px = (double)j.dh * j.dw;
+        tot += px;
+        if (!wants_gather(j, op) && tile_lds_bytes(tile_geom(j, op, tw, th), tw, th) <= KB_LDS_BUDGET)
+            fit += px;
+    }
+    return tot > 0 ? fit / tot : 1.0;
 }
 
-constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's widest box
+// Default tile shape of a batch group: small tiles (batches of small outputs
+// still produce many tiles), squarer ones when shrinking rotated warps would
+// not fit their boxes otherwise.
+static TileCfg default_batch_cfg(int op, bool f32, const std::vector<ImageJob> &imgs)
+{
+    std::vector<TileCfg> pref;
+    if (op == OP_WARP)
+        pref = f32 ? std::vector<TileCfg>{{1, 64, 1, 4, false}, {4, 8, 1, 1, false}}
+                   : std::vector<TileCfg>{{4, 16, 1, 1, false}, {4, 8, 1, 1, false}};
+    else
+        pref = {f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false}};
+    TileCfg best = pref[0];
+    double best_cov = -1;
+    for (const TileCfg &c : pref) {
+        const double cov = lds_coverage(op, c, imgs);
+        if (cov >= 0.95)
+            return c;
+        if (cov > best_cov) {
+            best_cov = cov;
+            best = c;
+        }
+    }
+    return best;
+}
 
 // Build the host-side job table of one operation group.  Items whose own box
 // would exceed the LDS budget (and large-ratio resizes) run every tile on the
 // global-gather path; the others set the launch-wide LDS geometry.
-void build_group(int op, bool f32, const std::vector<ImageJob> &imgs, BatchGroup &g, std::vector<TiledJob> &table)
+void build_group(int op, bool f32, int c, const std::vector<ImageJob> &imgs, BatchGroup &g,
+                 std::vector<TiledJob> &table, const TileCfg *force)
 {
     g.op = op;
-    g.cfg = batch_cfg(op, f32);
+    TileCfg tuned;
+    if (force)
+        g.cfg = *force;
+    else if (!imgs.empty() && tune_lookup(tune_key_batch(op, c, f32, imgs), &tuned))
+        g.cfg = tuned;
+    else
+        g.cfg = default_batch_cfg(op, f32, imgs);
     const int tw = g.cfg.txt * g.cfg.px * g.cfg.cpt;
     const int th = (KT_THREADS / g.cfg.txt) * g.cfg.rpt;
     table.clear();
@@ -228,8 +265,8 @@ kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src
     uint8_t *wsb = static_cast<uint8_t *>(workspace);
     BatchGroup groups[2];
     std::vector<TiledJob> tables[2];
-    build_group(OP_RESIZE, f32, rs, groups[0], tables[0]);
-    build_group(OP_WARP, f32, ws, groups[1], tables[1]);
+    build_group(OP_RESIZE, f32, c, rs, groups[0], tables[0], nullptr);
+    build_group(OP_WARP, f32, c, ws, groups[1], tables[1], nullptr);
     size_t off = 0;
     for (int k = 0; k < 2; k++) {
         if (groups[k].njobs == 0)
@@ -296,8 +333,8 @@ kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtyp
         return fail(KR_ERR_INVALID_ARGUMENT, "out of host memory");
     BatchGroup groups[2];
     std::vector<TiledJob> tables[2];
-    build_group(OP_RESIZE, f32, rs, groups[0], tables[0]);
-    build_group(OP_WARP, f32, ws, groups[1], tables[1]);
+    build_group(OP_RESIZE, f32, c, rs, groups[0], tables[0], nullptr);
+    build_group(OP_WARP, f32, c, ws, groups[1], tables[1], nullptr);
     const size_t bytes = kr_resize_batch_workspace_size(n);
     hipError_t err = hipMalloc(&p->table, bytes);
     if (err != hipSuccess) {
@@ -362,3 +399,85 @@ void kr_batch_plan_destroy(kr_batch_plan *plan)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ autotuning
+extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                                       kr_border border, float border_value, const kr_normalize *norm,
+                                       void *workspace, size_t workspace_bytes, int reps, void *stream, char *report,
+                                       size_t report_len)
+{
+    clear_error();
+    std::vector<ImageJob> imgs[2];
+    kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, imgs[0], imgs[1]);
+    if (st != KR_OK)
+        return st;
+    if (!tiled_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+    if (workspace_bytes < kr_resize_batch_workspace_size(n))
+        return fail(KR_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
+    if (reps < 1 || reps > 1000)
+        return fail(KR_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    const bool f32 = dst_t == KR_F32;
+    hipStream_t s = (hipStream_t)stream;
+    std::string rep;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(KR_ERR_HIP, "event creation failed");
+    kr_status result = KR_OK;
+    for (int k = 0; k < 2 && result == KR_OK; k++) {
+        if (imgs[k].empty())
+            continue;
+        const int op = k == 0 ? OP_RESIZE : OP_WARP;
+        TileCfg best{};
+        float best_ms = -1;
+        for (const TileCfg &cfg : batch_candidates(op)) {
+            BatchGroup g;
+            std::vector<TiledJob> table;
+            build_group(op, f32, c, imgs[k], g, table, &cfg);
+            if (g.lds > KT_LDS_CAP)
+                continue;
+            TiledJob *dev = static_cast<TiledJob *>(workspace);
+            hipError_t err = hipMemcpyAsync(dev, table.data(), table.size() * sizeof(TiledJob),
+                                            hipMemcpyHostToDevice, s);
+            g.jobs_dev = dev;
+            if (err == hipSuccess)
+                err = launch_group(g, c, dst_t, e, s);  // warm-up
+            if (err == hipSuccess)
+                err = hipEventRecord(a, s);
+            for (int r = 0; r < reps && err == hipSuccess; r++)
+                err = launch_group(g, c, dst_t, e, s);
+            if (err == hipSuccess)
+                err = hipEventRecord(b, s);
+            if (err == hipSuccess)
+                err = hipEventSynchronize(b);
+            float ms = 0;
+            if (err == hipSuccess)
+                err = hipEventElapsedTime(&ms, a, b);
+            if (err != hipSuccess) {
+                result = fail(KR_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(err));
+                break;
+            }
+            ms /= (float)reps;
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                best = cfg;
+            }
+        }
+        if (result == KR_OK && best_ms >= 0) {
+            const TuneKey key = tune_key_batch(op, c, f32, imgs[k]);
+            tune_store(key, best);
+            char line[256];
+            std::snprintf(line, sizeof line, "%s -> %s (%.1f us); ", tune_key_string(key).c_str(),
+                          tune_cfg_string(best).c_str(), best_ms * 1000.0f);
+            rep += line;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (result == KR_OK && report && report_len > 0)
+        std::snprintf(report, report_len, "%s", rep.c_str());
+    return result;
+}

@@ -21,8 +21,10 @@ struct BatchGroup {
 };
 
 // Host-side job table of one operation group (tile prefix sums, launch-wide
-// LDS geometry).
-void build_group(int op, bool f32, const std::vector<ImageJob> &imgs, BatchGroup &g, std::vector<TiledJob> &table);
+// LDS geometry).  force: explicit configuration, else the tuned one for this
+// batch class, else the default.
+void build_group(int op, bool f32, int c, const std::vector<ImageJob> &imgs, BatchGroup &g,
+                 std::vector<TiledJob> &table, const TileCfg *force);
 
 // Launch one group whose job table is already on the device (g.jobs_dev).
 hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue &e, hipStream_t s);

@@ -54,7 +54,7 @@ struct HipExec {
         std::vector<TiledJob> tables[2];
         size_t off = 0;
         for (int k = 0; k < 2; k++) {
-            build_group(k == 0 ? OP_RESIZE : OP_WARP, dt == KR_F32, imgs[k], groups[k], tables[k]);
+            build_group(k == 0 ? OP_RESIZE : OP_WARP, dt == KR_F32, c, imgs[k], groups[k], tables[k], nullptr);
             if (groups[k].njobs == 0)
                 continue;
             std::memcpy(static_cast<uint8_t *>(sl.staging) + off, tables[k].data(),

@@ -7,6 +7,7 @@
 
 #include "tiled.h"
 #include "tiled_launch.h"
+#include "tune.h"
 
 namespace kr {
 
@@ -135,11 +136,6 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
     return hipGetLastError();
 }
 
-// Tile configurations (PX, TXT, CPT, RPT) compiled per operation.
-#define KR_WARP_CFGS(X) X(4, 16, 1, 2) X(4, 16, 1, 4) X(1, 64, 1, 8) X(1, 64, 1, 16)
-#define KR_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 32, 1, 2) X(4, 64, 1, 1) X(4, 64, 1, 2) \
-    X(1, 64, 2, 4) X(1, 64, 4, 2)
-
 template <int OP, int C, bool F32>
 static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epilogue &e, hipStream_t s, bool gather,
                                bool &fits)
@@ -193,8 +189,12 @@ static int default_cfgs(int op, bool f32, TileCfg *out)
 template <int OP, int C, bool F32>
 static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
-    TileCfg cfgs[6];
-    const int n = default_cfgs(OP, F32, cfgs);
+    TileCfg cfgs[8];
+    int n = 0;
+    TileCfg tuned;
+    if (tune_lookup(tune_key_image(OP, C, F32, j), &tuned))
+        cfgs[n++] = tuned;
+    n += default_cfgs(OP, F32, cfgs + n);
     for (int i = 0; i < n; i++) {
         bool fits = false;
         const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, false, fits);
@@ -203,6 +203,25 @@ static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
     }
     bool fits = false;
     return launch_shape<OP, C, F32>(cfgs[n - 1], j, e, s, true, fits);
+}
+
+hipError_t launch_tiled_cfg(int op, int c, kr_dtype dt, const TileCfg &cfg, const ImageJob &j, const Epilogue &e,
+                            hipStream_t s, bool &fits)
+{
+    const bool f = dt == KR_F32;
+    fits = false;
+    if (op == OP_WARP) {
+        if (c == 3)
+            return f ? launch_shape<OP_WARP, 3, true>(cfg, j, e, s, false, fits)
+                     : launch_shape<OP_WARP, 3, false>(cfg, j, e, s, false, fits);
+        return f ? launch_shape<OP_WARP, 4, true>(cfg, j, e, s, false, fits)
+                 : launch_shape<OP_WARP, 4, false>(cfg, j, e, s, false, fits);
+    }
+    if (c == 3)
+        return f ? launch_shape<OP_RESIZE, 3, true>(cfg, j, e, s, false, fits)
+                 : launch_shape<OP_RESIZE, 3, false>(cfg, j, e, s, false, fits);
+    return f ? launch_shape<OP_RESIZE, 4, true>(cfg, j, e, s, false, fits)
+             : launch_shape<OP_RESIZE, 4, false>(cfg, j, e, s, false, fits);
 }
 
 bool tiled_supported(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 4); }

@@ -19,6 +19,19 @@ struct TileCfg {
     bool persistent;
 };
 
+// Compiled tile configurations (PX, TXT, CPT, RPT) per operation: the
+// per-image kernels and the batched work-list kernels.
+#define KR_WARP_CFGS(X) X(4, 16, 1, 2) X(4, 16, 1, 4) X(4, 8, 1, 1) X(1, 64, 1, 8) X(1, 64, 1, 16)
+#define KR_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 32, 1, 2) X(4, 64, 1, 1) X(4, 64, 1, 2) \
+    X(1, 64, 2, 4) X(1, 64, 4, 2)
+#define KR_BATCH_WARP_CFGS(X) X(4, 16, 1, 1) X(4, 16, 1, 2) X(4, 8, 1, 1) X(1, 64, 1, 4) X(1, 64, 1, 8)
+#define KR_BATCH_RESIZE_CFGS(X) X(4, 16, 1, 1) X(1, 64, 1, 4) X(1, 64, 2, 4)
+
+// Launch one image with an explicit configuration; fits = false (nothing
+// launched) when its LDS footprint exceeds the per-workgroup budget.
+hipError_t launch_tiled_cfg(int op, int c, kr_dtype dt, const TileCfg &cfg, const ImageJob &j, const Epilogue &e,
+                            hipStream_t s, bool &fits);
+
 int device_cus();
 int persistent_grid(int ntiles, int per_cu);
 TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th);

@@ -1,0 +1,37 @@
+// tune.h -- autotuned choice of tile configuration (process-wide table).
+//
+// A key names a class of launches: operation, channels, output type, single
+// image or batch, the source-pixels-per-output-pixel class (half-octaves of
+// the area ratio) and the output-size class (factors of 4 in pixels).  The
+// table maps keys to the configuration the tuner measured fastest; launchers
+// try it before their defaults.  KR_AUTOTUNE_CACHE names a text file loaded
+// on first use.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "tiled_launch.h"
+
+namespace kr {
+
+struct TuneKey {
+    int op, c, f32, batch, sclass, zclass;
+};
+
+TuneKey tune_key_image(int op, int c, bool f32, const ImageJob &j);
+TuneKey tune_key_batch(int op, int c, bool f32, const std::vector<ImageJob> &imgs);
+bool tune_lookup(const TuneKey &k, TileCfg *cfg);
+void tune_store(const TuneKey &k, const TileCfg &cfg);
+void tune_clear();
+std::string tune_key_string(const TuneKey &k);
+std::string tune_cfg_string(const TileCfg &c);
+std::string tune_dump();
+bool tune_load_text(const std::string &text);
+
+// Every compiled configuration of an operation (single image: both grid
+// modes; batch: one-tile-per-block grids).
+std::vector<TileCfg> image_candidates(int op);
+std::vector<TileCfg> batch_candidates(int op);
+
+}  // namespace kr

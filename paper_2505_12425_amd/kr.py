@@ -87,6 +87,18 @@ def lib():
         L.kr_batch_plan_launch.restype = i
         L.kr_batch_plan_destroy.argtypes = [vp]
         L.kr_batch_plan_destroy.restype = None
+    if hasattr(L, "kr_autotune_image"):
+        cp, sz = ctypes.c_char_p, ctypes.c_size_t
+        L.kr_autotune_image.argtypes = [i, vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, i, vp, cp, sz]
+        L.kr_autotune_image.restype = i
+        L.kr_autotune_batch.argtypes = [ctypes.POINTER(BatchItem), i, i, i, i, i, f, npp, vp, sz, i, vp, cp, sz]
+        L.kr_autotune_batch.restype = i
+        L.kr_autotune_save.argtypes = [cp, sz]
+        L.kr_autotune_save.restype = sz
+        L.kr_autotune_load.argtypes = [cp]
+        L.kr_autotune_load.restype = i
+        L.kr_autotune_clear.argtypes = []
+        L.kr_autotune_clear.restype = None
     _lib = L
     return L
 
@@ -233,6 +245,58 @@ def resize_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean
         workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
     check(lib().kr_resize_batch(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
                                 workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+# ---------------------------------------------------------------- autotuning
+def autotune_image(op: str, src, dst, m=None, inverse: bool = False, border: int = REPLICATE,
+                   border_value: float = 0.0, mean=None, std=None, reps: int = 20, stream=None) -> str:
+    """kr_autotune_image: time every tile configuration on this image and record
+    the fastest for its class; dst receives the (correct) output.  Returns the
+    one-line report."""
+    sp, sh, sw, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if dc != c:
+        raise ValueError("src and dst channel counts differ")
+    rep = ctypes.create_string_buffer(512)
+    is_warp = op == "warp"
+    check(lib().kr_autotune_image(OP_WARP if is_warp else OP_RESIZE, sp, sh, sw, c, st, dp_, dh, dw, dt,
+                                  _m6(m) if is_warp else None, WARP_INVERSE_MAP if inverse else 0, border,
+                                  float(border_value), _normalize(mean, std, c), int(reps), _stream(stream),
+                                  rep, len(rep)))
+    return rep.value.decode()
+
+
+def autotune_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
+                   workspace=None, reps: int = 10, stream=None) -> str:
+    """kr_autotune_batch: tune the batch's resize and warp launches (outputs are
+    written, correctly, as by resize_batch).  Returns the report."""
+    import torch
+    arr, n, c, st, dt = _batch_items(specs)
+    if n == 0:
+        return ""
+    if workspace is None:
+        workspace = torch.empty(batch_workspace_size(n), dtype=torch.uint8, device="cuda")
+    rep = ctypes.create_string_buffer(1024)
+    check(lib().kr_autotune_batch(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
+                                  workspace.data_ptr(), workspace.numel() * workspace.element_size(), int(reps),
+                                  _stream(stream), rep, len(rep)))
+    return rep.value.decode()
+
+
+def autotune_save() -> str:
+    """The tuned table as text (kr_autotune_save)."""
+    need = int(lib().kr_autotune_save(None, 0))
+    buf = ctypes.create_string_buffer(need)
+    lib().kr_autotune_save(buf, need)
+    return buf.value.decode()
+
+
+def autotune_load(text: str) -> None:
+    check(lib().kr_autotune_load(text.encode()))
+
+
+def autotune_clear() -> None:
+    lib().kr_autotune_clear()
 
 
 class BatchPlan:

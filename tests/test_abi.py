@@ -199,3 +199,58 @@ def test_server_config_validation():
         == kr.ERR_INVALID_ARGUMENT
     assert h.value is None
     L.kr_server_destroy(None)
+
+
+def test_autotune_table_roundtrip_and_validation():
+    kr.autotune_clear()
+    assert kr.autotune_save().strip() == "# op c f32 batch sclass zclass px txt cpt rpt persistent"
+    good = ("# comment\n"
+            "1 3 0 0 0 11 4 16 1 4 1\n"
+            "0 4 1 0 -4 10 1 64 2 4 0\n"
+            "1 3 1 1 2 13 4 8 1 1 0\n")
+    kr.autotune_load(good)
+    lines = [ln for ln in kr.autotune_save().splitlines() if not ln.startswith("#")]
+    assert sorted(lines) == sorted(ln for ln in good.splitlines() if not ln.startswith("#"))
+    before = kr.autotune_save()
+    for bad in ["1 3 0 0 0 11 4 16 1 4\n",           # short line
+                "1 3 0 0 0 11 4 16 1 4 1 9\n",       # trailing field
+                "1 3 0 0 0 11 4 12 1 4 1\n",         # no such configuration
+                "1 3 0 1 0 11 4 16 1 4 1\n",         # batches have no persistent grids
+                "2 3 0 0 0 11 4 16 1 4 1\n",         # unknown op
+                "1 2 0 0 0 11 4 16 1 4 1\n",         # channel count without configurations
+                "0 3 0 0 0 11 1 64 2 4 0\nbogus\n"]:  # one bad line rejects the whole text
+        with pytest.raises(kr.KrError) as e:
+            kr.autotune_load(bad)
+        assert e.value.status == kr.ERR_INVALID_ARGUMENT
+        assert kr.autotune_save() == before
+    # truncated save: NUL-terminated prefix, full length reported
+    buf = ctypes.create_string_buffer(10)
+    need = kr.lib().kr_autotune_save(buf, 10)
+    assert need == len(before) + 1 and buf.value.decode() == before[:9]
+    kr.autotune_clear()
+    assert kr.autotune_save() == "# op c f32 batch sclass zclass px txt cpt rpt persistent\n"
+
+
+def test_autotune_validation():
+    L = kr.lib()
+    rep = ctypes.create_string_buffer(64)
+    m = (ctypes.c_double * 6)(1, 0, 0, 0, 1, 0)
+    args = lambda **kw: [kw.get("op", 0), A, 480, 640, kw.get("c", 3), kw.get("st", kr.U8), B, 240, 320,
+                         kr.U8, m, kw.get("flags", 0), kr.REPLICATE, 0.0, None, kw.get("reps", 5), None, rep, 64]
+    assert L.kr_autotune_image(*args(op=5)) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_image(*args(reps=0)) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_image(*args(reps=1001)) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_image(*args(c=1)) == kr.ERR_UNSUPPORTED
+    assert L.kr_autotune_image(*args(op=1, flags=4)) == kr.ERR_INVALID_ARGUMENT
+    sing = (ctypes.c_double * 6)(1, 2, 0, 2, 4, 0)
+    a = args(op=1)
+    a[10] = sing
+    assert L.kr_autotune_image(*a) == kr.ERR_SINGULAR_MATRIX
+    ws = A + 0x10000000
+    assert L.kr_autotune_batch(batch_items(dst_stride=0), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 5, None,
+                               rep, 64) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 16, 5, None, rep, 64) \
+        == kr.ERR_WORKSPACE_TOO_SMALL
+    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 0, None, rep, 64) \
+        == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_load(None) == kr.ERR_INVALID_ARGUMENT
