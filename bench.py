@@ -25,7 +25,6 @@ the 2x2 taps at 128-byte line granularity + output bytes.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,7 +35,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2505_12425_amd.profsum import kernel_source_sha  # noqa: E402
+
 HBM_PEAK_GBPS = 8000.0
+TUNE_FILE = os.path.join(ROOT, "paper_2505_12425_amd", "tuned_mi355x.txt")
+SCRUB_BYTES = 512 << 20  # > the 256 MB last-level cache: evicts a source between tuner launches
 LINE = 128
 
 
@@ -90,16 +93,6 @@ def warp_touched_bytes(h, w, dh, dw, inv, c=3, esize=1, border_constant=True) ->
 
 
 # ---------------------------------------------------------------- helpers
-def _sha_of_kernel_sources() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2505_12425_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(name.encode())
-            h.update(open(os.path.join(csrc, name), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def _traffic_from_profiles(kernel: str):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they were
     taken on the current kernel sources (else None)."""
@@ -111,7 +104,7 @@ def _traffic_from_profiles(kernel: str):
     except ValueError:
         return None
     ent = rec.get("kernels", {}).get(kernel)
-    if not ent or rec.get("source_sha") != _sha_of_kernel_sources():
+    if not ent or rec.get("source_sha") != kernel_source_sha():
         return None
     return ent.get("bytes_per_launch")
 
@@ -190,54 +183,55 @@ def bench_4k(args, torch, kr, wl):
     px_per_step = sum(px.values())
 
     tuned = {}
-    if args.autotune:
+    if args.tune_mode == "live":
+        # timed with the caches scrubbed before each launch: the loops below
+        # stream every source from HBM too
+        scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device="cuda")
         for n in names:
             d = outs[n]
             if n.startswith("resize"):
-                tuned[n] = kr.autotune_image("resize", srcs[0], d, border=kr.REPLICATE, reps=20)
+                tuned[n] = kr.autotune_image("resize", srcs[0], d, border=kr.REPLICATE, reps=15, scrub=scrub)
             else:
-                tuned[n] = kr.autotune_image("warp", srcs[0], d, m, border=kr.CONSTANT, reps=20)
-    for i in range(args.warmup):
+                tuned[n] = kr.autotune_image("warp", srcs[0], d, m, border=kr.CONSTANT, reps=15, scrub=scrub)
+        del scrub
+    # Every launch reads a source copy that the previous (copies - 1) launches
+    # did not touch, so no launch finds its source in the caches.
+    k = 0
+    for _ in range(args.warmup):
         for n in names:
-            launch(n, srcs[i % copies])
+            launch(n, srcs[k % copies])
+            k += 1
     torch.cuda.synchronize()
-    evs = {n: [] for n in names}
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record()
-    for i in range(args.steps):
-        src = srcs[i % copies]
+    for _ in range(args.steps):
         for n in names:
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            launch(n, src)
-            b.record()
-            evs[n].append((a, b))
+            launch(n, srcs[k % copies])
+            k += 1
     t_end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / args.steps
-    # per-kernel duration: the same kernel launched back to back (rotating
-    # sources) between one pair of events, divided by the launch count; the
-    # per-launch event pairs of the step loop are reported beside it.
+    # per-kernel duration: that kernel alone, launched back to back on the same
+    # stream (rotating cold sources) between one event pair, / launch count
     kern = {}
     reps = max(args.steps, 20)
     for n in names:
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
-        for i in range(reps):
-            launch(n, srcs[i % copies])
+        for _ in range(reps):
+            launch(n, srcs[k % copies])
+            k += 1
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / reps
-        ms_ev = float(np.mean([x.elapsed_time(y) for x, y in evs[n]]))
         gbps = alg[n] / (ms * 1e-3) / 1e9
-        kern[n] = {"avg_us": round(ms * 1e3, 3), "avg_us_event_pair": round(ms_ev * 1e3, 3),
-                   "alg_bytes": alg[n], "GBps": round(gbps, 1),
-                   "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(px[n] / (ms * 1e-3) / 1e9, 2)}
+        kern[n] = {"avg_us": round(ms * 1e3, 3), "launches": reps, "alg_bytes": alg[n], "GBps": round(gbps, 1),
+                   "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(px[n] / (ms * 1e-3) / 1e9, 2),
+                   "traffic": _traffic_from_profiles(n)}
     dom = max(names, key=lambda n: kern[n]["avg_us"])
     return {
         "value": px_per_step * args.steps / (total_ms * 1e-3) / 1e9,
@@ -277,8 +271,12 @@ def bench_batch(args, torch, kr, wl):
     mean, std = wl.IMAGENET_MEAN, wl.IMAGENET_STD
     specs = [{"op": "resize", "src": s, "dst": d} for s, d in zip(srcs, dsts)]
     ws = torch.empty(kr.batch_workspace_size(len(specs)), dtype=torch.uint8, device="cuda")
-    tuned = (kr.autotune_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws, reps=10)
-             if args.autotune else "")
+    tuned = ""
+    if args.tune_mode == "live":
+        scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device="cuda")
+        tuned = kr.autotune_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws, reps=10,
+                                  scrub=scrub)
+        del scrub
     plan = kr.BatchPlan(specs, border=kr.REPLICATE, mean=mean, std=std)
 
     def per_image():
@@ -330,7 +328,11 @@ def bench_warpbatch(args, torch, kr, wl):
         mats.append(wl.random_affine_batch(1080, 1920, rng))
     dsts = [torch.empty((1080, 1920, 3), dtype=torch.uint8, device="cuda") for _ in srcs]
     specs = [{"op": "warp", "src": s, "dst": d, "m": m} for s, d, m in zip(srcs, dsts, mats)]
-    tuned = kr.autotune_batch(specs, border=kr.CONSTANT, reps=10) if args.autotune else ""
+    tuned = ""
+    if args.tune_mode == "live":
+        scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device="cuda")
+        tuned = kr.autotune_batch(specs, border=kr.CONSTANT, reps=10, scrub=scrub)
+        del scrub
     plan = kr.BatchPlan(specs, border=kr.CONSTANT)
 
     def per_image():
@@ -419,16 +421,25 @@ def bench_serve(args, torch, kr, wl):
     }
 
 
+def _save_tuning(args, kr):
+    if args.save_tune:
+        with open(args.save_tune, "w") as f:
+            f.write(kr.autotune_save())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve"])
-    ap.add_argument("--cold-copies", type=int, default=12)
+    ap.add_argument("--cold-copies", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="keep the built-in tile configurations instead of tuning them first")
+    ap.add_argument("--tune", default="auto", choices=["auto", "file", "live", "off"],
+                    help="tile configurations: file = load --tune-file (the table the tuner wrote on MI355X), "
+                         "live = run the autotuner first, off = built-in defaults; auto = file if it exists")
+    ap.add_argument("--tune-file", default=TUNE_FILE)
+    ap.add_argument("--save-tune", default=None, help="write the tuning table here at the end")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--budget-mb", type=int, default=2048)
@@ -445,8 +456,17 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     kr.lib()
+    args.tune_mode = args.tune if args.tune != "auto" else ("file" if os.path.exists(args.tune_file) else "live")
+    kr.autotune_clear()
+    if args.tune_mode == "file":
+        kr.autotune_load(open(args.tune_file).read())
+    tuning = {"mode": args.tune_mode}
+    if args.tune_mode == "file":
+        tuning["file"] = os.path.relpath(args.tune_file, ROOT)
     common = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    # the copy ceiling (also the calibration point of HBM byte counters)
+    copy_gbps = _hbm_copy_ceiling(torch, kr)
     if args.workload != "4k":
         fn = {"batch": bench_batch, "warpbatch": bench_warpbatch, "serve": bench_serve}[args.workload]
         r = fn(args, torch, kr, wl)
@@ -454,10 +474,14 @@ def main():
         out.update(common)
         out["ms_per_step"] = r.pop("ms_per_step")
         out["dtype"] = "u8 fixed-point / f32"
+        tuning["reports"] = r.pop("autotune", None)
+        if "roofline" in r:
+            r["roofline"]["copy_ceiling_GBps"] = round(copy_gbps, 1)
         out.update(r)
+        out["tuning"] = tuning
+        _save_tuning(args, kr)
         print(json.dumps(out))
         return
-    copy_gbps = _hbm_copy_ceiling(torch, kr)
     r = bench_4k(args, torch, kr, wl)
     dom = r["dominant"]
     k = r["kernels"][dom]
@@ -471,8 +495,10 @@ def main():
         "value": round(r["value"], 3), "unit": "Gpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8 fixed-point / f32", "data": "synthetic",
-        "config": r["config"], "roofline": roof, "kernels": r["kernels"], "autotune": r["autotune"],
+        "config": r["config"], "roofline": roof, "kernels": r["kernels"],
+        "tuning": dict(tuning, reports=r["autotune"]),
     }
+    _save_tuning(args, kr)
     if not args.no_cpu_baseline:
         img, m = r["cpu_args"]
         out["cpu_baseline"] = _cpu_baseline_4k(img, m, args.cpu_seconds)

@@ -239,10 +239,16 @@ void kr_server_destroy(kr_server *server);
  * kr_warp_affine (op 1), plus reps timed launches per configuration (1..1000).
  * It launches on stream, synchronises it, and leaves the correct output in
  * dst.  report: NULL, or a host buffer receiving a one-line summary.
+ * scrub: NULL (launches timed back to back: a source that stays in the
+ * caches) or a DEVICE buffer of scrub_bytes (16-byte aligned, >= 32, best
+ * larger than the 256 MB last-level cache) overlapping no other argument,
+ * whose contents the tuner overwrites before each timed launch so that the
+ * source is read from HBM, as in a stream of distinct images; the median of
+ * those reps is then used.
  * Only u8 sources with 3 or 4 channels have configurations
  * (KR_ERR_UNSUPPORTED otherwise).
- * kr_autotune_batch: same arguments as kr_resize_batch plus reps and report;
- * tunes the resize and the warp launch of the batch separately.
+ * kr_autotune_batch: same arguments as kr_resize_batch plus reps, scrub and
+ * report; tunes the resize and the warp launch of the batch separately.
  * kr_autotune_save: writes the table as text into buf (truncated to len
  * bytes, NUL-terminated) and returns the bytes the full text needs.
  * kr_autotune_load: merges a text table (as written by kr_autotune_save);
@@ -252,11 +258,12 @@ void kr_server_destroy(kr_server *server);
  */
 kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
                             int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags, kr_border border,
-                            float border_value, const kr_normalize *norm, int reps, void *stream, char *report,
-                            size_t report_len);
+                            float border_value, const kr_normalize *norm, int reps, void *scrub,
+                            size_t scrub_bytes, void *stream, char *report, size_t report_len);
 kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
                             kr_border border, float border_value, const kr_normalize *norm, void *workspace,
-                            size_t workspace_bytes, int reps, void *stream, char *report, size_t report_len);
+                            size_t workspace_bytes, int reps, void *scrub, size_t scrub_bytes, void *stream,
+                            char *report, size_t report_len);
 size_t kr_autotune_save(char *buf, size_t len);
 kr_status kr_autotune_load(const char *text);
 void kr_autotune_clear(void);

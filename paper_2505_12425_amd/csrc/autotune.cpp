@@ -10,12 +10,25 @@
 
 using namespace kr;
 
+namespace kr {
+
+kr_status check_scrub(const void *scrub, size_t bytes)
+{
+    if (!scrub)
+        return KR_OK;
+    if (reinterpret_cast<uintptr_t>(scrub) % 16 != 0 || bytes < 32)
+        return fail(KR_ERR_INVALID_ARGUMENT, "scrub must be 16-byte aligned and at least 32 bytes");
+    return KR_OK;
+}
+
+}  // namespace kr
+
 extern "C" {
 
 kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
                             int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags, kr_border border,
-                            float border_value, const kr_normalize *norm, int reps, void *stream, char *report,
-                            size_t report_len)
+                            float border_value, const kr_normalize *norm, int reps, void *scrub, size_t scrub_bytes,
+                            void *stream, char *report, size_t report_len)
 {
     clear_error();
     if (op != KR_OP_RESIZE && op != KR_OP_WARP)
@@ -27,6 +40,9 @@ kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c
         return fail(KR_ERR_UNSUPPORTED, "only u8 sources with 3 or 4 channels have tunable configurations");
     if (reps < 1 || reps > 1000)
         return fail(KR_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");
+    st = check_scrub(scrub, scrub_bytes);
+    if (st != KR_OK)
+        return st;
     ImageJob j;
     std::memset(&j, 0, sizeof j);
     if (op == KR_OP_WARP) {
@@ -39,45 +55,24 @@ kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c
     j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
     const Epilogue e = make_epilogue(c, border, border_value, norm);
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-        if (a)
-            (void)hipEventDestroy(a);
-        return fail(KR_ERR_HIP, "event creation failed");
-    }
     TileCfg best{};
     float best_ms = -1;
-    kr_status result = KR_OK;
     for (const TileCfg &cfg : image_candidates(op)) {
         bool fits = false;
         hipError_t err = launch_tiled_cfg(op, c, dst_t, cfg, j, e, s, fits);  // warm-up
         if (err == hipSuccess && !fits)
             continue;
-        if (err == hipSuccess)
-            err = hipEventRecord(a, s);
-        for (int r = 0; r < reps && err == hipSuccess; r++)
-            err = launch_tiled_cfg(op, c, dst_t, cfg, j, e, s, fits);
-        if (err == hipSuccess)
-            err = hipEventRecord(b, s);
-        if (err == hipSuccess)
-            err = hipEventSynchronize(b);
         float ms = 0;
         if (err == hipSuccess)
-            err = hipEventElapsedTime(&ms, a, b);
-        if (err != hipSuccess) {
-            result = fail(KR_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(err));
-            break;
-        }
-        ms /= (float)reps;
+            err = time_launches([&] { return launch_tiled_cfg(op, c, dst_t, cfg, j, e, s, fits); }, reps, scrub,
+                                scrub_bytes, s, ms);
+        if (err != hipSuccess)
+            return fail(KR_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(err));
         if (best_ms < 0 || ms < best_ms) {
             best_ms = ms;
             best = cfg;
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    if (result != KR_OK)
-        return result;
     if (best_ms < 0)
         return KR_OK;  // no tiled configuration fits: launches keep the global-gather path
     const TuneKey key = tune_key_image(op, c, dst_t == KR_F32, j);

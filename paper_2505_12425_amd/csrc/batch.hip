@@ -403,8 +403,8 @@ void kr_batch_plan_destroy(kr_batch_plan *plan)
 // ------------------------------------------------------------------ autotuning
 extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
                                        kr_border border, float border_value, const kr_normalize *norm,
-                                       void *workspace, size_t workspace_bytes, int reps, void *stream, char *report,
-                                       size_t report_len)
+                                       void *workspace, size_t workspace_bytes, int reps, void *scrub,
+                                       size_t scrub_bytes, void *stream, char *report, size_t report_len)
 {
     clear_error();
     std::vector<ImageJob> imgs[2];
@@ -419,13 +419,13 @@ extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c,
         return fail(KR_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
     if (reps < 1 || reps > 1000)
         return fail(KR_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");
+    st = check_scrub(scrub, scrub_bytes);
+    if (st != KR_OK)
+        return st;
     const Epilogue e = make_epilogue(c, border, border_value, norm);
     const bool f32 = dst_t == KR_F32;
     hipStream_t s = (hipStream_t)stream;
     std::string rep;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-        return fail(KR_ERR_HIP, "event creation failed");
     kr_status result = KR_OK;
     for (int k = 0; k < 2 && result == KR_OK; k++) {
         if (imgs[k].empty())
@@ -440,27 +440,20 @@ extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c,
             if (g.lds > KT_LDS_CAP)
                 continue;
             TiledJob *dev = static_cast<TiledJob *>(workspace);
+            // the host table must outlive the copy: time_launches synchronises the stream
             hipError_t err = hipMemcpyAsync(dev, table.data(), table.size() * sizeof(TiledJob),
                                             hipMemcpyHostToDevice, s);
             g.jobs_dev = dev;
             if (err == hipSuccess)
                 err = launch_group(g, c, dst_t, e, s);  // warm-up
-            if (err == hipSuccess)
-                err = hipEventRecord(a, s);
-            for (int r = 0; r < reps && err == hipSuccess; r++)
-                err = launch_group(g, c, dst_t, e, s);
-            if (err == hipSuccess)
-                err = hipEventRecord(b, s);
-            if (err == hipSuccess)
-                err = hipEventSynchronize(b);
             float ms = 0;
             if (err == hipSuccess)
-                err = hipEventElapsedTime(&ms, a, b);
+                err = time_launches([&] { return launch_group(g, c, dst_t, e, s); }, reps, scrub, scrub_bytes, s,
+                                    ms);
             if (err != hipSuccess) {
                 result = fail(KR_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(err));
                 break;
             }
-            ms /= (float)reps;
             if (best_ms < 0 || ms < best_ms) {
                 best_ms = ms;
                 best = cfg;
@@ -475,8 +468,6 @@ extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c,
             rep += line;
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
     if (result == KR_OK && report && report_len > 0)
         std::snprintf(report, report_len, "%s", rep.c_str());
     return result;

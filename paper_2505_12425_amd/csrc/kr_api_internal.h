@@ -18,5 +18,7 @@ kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void
 Epilogue make_epilogue(int c, kr_border border, float bval, const kr_normalize *norm);
 kr_status check_matrix(const double m[6], int flags, double inv[6]);
 kr_status invert_affine_impl(const double m[6], double inv[6]);
+// Tuner scrub buffer: NULL, or 16-byte aligned and >= 32 bytes.
+kr_status check_scrub(const void *scrub, size_t bytes);
 
 }  // namespace kr

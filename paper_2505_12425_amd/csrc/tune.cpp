@@ -191,6 +191,42 @@ bool tune_load_text(const std::string &text)
     return true;
 }
 
+hipError_t time_launches(const std::function<hipError_t()> &launch, int reps, void *scrub, size_t scrub_bytes,
+                         hipStream_t s, float &ms)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t err = hipEventCreate(&a);
+    if (err == hipSuccess)
+        err = hipEventCreate(&b);
+    std::vector<float> t;
+    const size_t half = scrub_bytes / 2 / 16 * 16;
+    for (int r = 0; r < (scrub ? reps : 1) && err == hipSuccess; r++) {
+        if (scrub)
+            err = launch_copy(static_cast<uint8_t *>(scrub) + half, scrub, half, s);
+        if (err == hipSuccess)
+            err = hipEventRecord(a, s);
+        for (int k = 0; k < (scrub ? 1 : reps) && err == hipSuccess; k++)
+            err = launch();
+        if (err == hipSuccess)
+            err = hipEventRecord(b, s);
+        if (err == hipSuccess)
+            err = hipEventSynchronize(b);
+        float x = 0;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&x, a, b);
+        t.push_back(scrub ? x : x / (float)reps);
+    }
+    if (a)
+        (void)hipEventDestroy(a);
+    if (b)
+        (void)hipEventDestroy(b);
+    if (err == hipSuccess) {
+        std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+        ms = t[t.size() / 2];
+    }
+    return err;
+}
+
 std::vector<TileCfg> image_candidates(int op)
 {
     std::vector<TileCfg> v;

@@ -8,6 +8,7 @@
 // on first use.
 #pragma once
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -33,5 +34,13 @@ bool tune_load_text(const std::string &text);
 // modes; batch: one-tile-per-block grids).
 std::vector<TileCfg> image_candidates(int op);
 std::vector<TileCfg> batch_candidates(int op);
+
+// Duration (ms) of one call of `launch` on stream s.  Without a scrub buffer:
+// reps calls back to back between one event pair, averaged.  With one: each
+// call timed alone right after the buffer's first half has been copied over
+// its second (which evicts the caller's source from the caches, as for a
+// source streamed from HBM), median of reps.  Synchronises s.
+hipError_t time_launches(const std::function<hipError_t()> &launch, int reps, void *scrub, size_t scrub_bytes,
+                         hipStream_t s, float &ms);
 
 }  // namespace kr

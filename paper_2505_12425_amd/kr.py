@@ -89,9 +89,10 @@ def lib():
         L.kr_batch_plan_destroy.restype = None
     if hasattr(L, "kr_autotune_image"):
         cp, sz = ctypes.c_char_p, ctypes.c_size_t
-        L.kr_autotune_image.argtypes = [i, vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, i, vp, cp, sz]
+        L.kr_autotune_image.argtypes = [i, vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, i, vp, sz, vp, cp, sz]
         L.kr_autotune_image.restype = i
-        L.kr_autotune_batch.argtypes = [ctypes.POINTER(BatchItem), i, i, i, i, i, f, npp, vp, sz, i, vp, cp, sz]
+        L.kr_autotune_batch.argtypes = [ctypes.POINTER(BatchItem), i, i, i, i, i, f, npp, vp, sz, i, vp, sz, vp,
+                                        cp, sz]
         L.kr_autotune_batch.restype = i
         L.kr_autotune_save.argtypes = [cp, sz]
         L.kr_autotune_save.restype = sz
@@ -248,11 +249,18 @@ def resize_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean
 
 
 # ---------------------------------------------------------------- autotuning
+def _scrub(scrub):
+    if scrub is None:
+        return None, 0
+    return scrub.data_ptr(), scrub.numel() * scrub.element_size()
+
+
 def autotune_image(op: str, src, dst, m=None, inverse: bool = False, border: int = REPLICATE,
-                   border_value: float = 0.0, mean=None, std=None, reps: int = 20, stream=None) -> str:
+                   border_value: float = 0.0, mean=None, std=None, reps: int = 20, scrub=None, stream=None) -> str:
     """kr_autotune_image: time every tile configuration on this image and record
-    the fastest for its class; dst receives the (correct) output.  Returns the
-    one-line report."""
+    the fastest for its class; dst receives the (correct) output.  scrub: None
+    or a device tensor (> 256 MB) overwritten before each timed launch so the
+    source comes from HBM.  Returns the one-line report."""
     sp, sh, sw, c, st = _image(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if dc != c:
@@ -261,13 +269,13 @@ def autotune_image(op: str, src, dst, m=None, inverse: bool = False, border: int
     is_warp = op == "warp"
     check(lib().kr_autotune_image(OP_WARP if is_warp else OP_RESIZE, sp, sh, sw, c, st, dp_, dh, dw, dt,
                                   _m6(m) if is_warp else None, WARP_INVERSE_MAP if inverse else 0, border,
-                                  float(border_value), _normalize(mean, std, c), int(reps), _stream(stream),
-                                  rep, len(rep)))
+                                  float(border_value), _normalize(mean, std, c), int(reps), *_scrub(scrub),
+                                  _stream(stream), rep, len(rep)))
     return rep.value.decode()
 
 
 def autotune_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
-                   workspace=None, reps: int = 10, stream=None) -> str:
+                   workspace=None, reps: int = 10, scrub=None, stream=None) -> str:
     """kr_autotune_batch: tune the batch's resize and warp launches (outputs are
     written, correctly, as by resize_batch).  Returns the report."""
     import torch
@@ -279,7 +287,7 @@ def autotune_batch(specs, border: int = REPLICATE, border_value: float = 0.0, me
     rep = ctypes.create_string_buffer(1024)
     check(lib().kr_autotune_batch(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
                                   workspace.data_ptr(), workspace.numel() * workspace.element_size(), int(reps),
-                                  _stream(stream), rep, len(rep)))
+                                  *_scrub(scrub), _stream(stream), rep, len(rep)))
     return rep.value.decode()
 
 

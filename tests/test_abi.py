@@ -236,21 +236,26 @@ def test_autotune_validation():
     rep = ctypes.create_string_buffer(64)
     m = (ctypes.c_double * 6)(1, 0, 0, 0, 1, 0)
     args = lambda **kw: [kw.get("op", 0), A, 480, 640, kw.get("c", 3), kw.get("st", kr.U8), B, 240, 320,
-                         kr.U8, m, kw.get("flags", 0), kr.REPLICATE, 0.0, None, kw.get("reps", 5), None, rep, 64]
+                         kr.U8, m, kw.get("flags", 0), kr.REPLICATE, 0.0, None, kw.get("reps", 5),
+                         kw.get("scrub", None), kw.get("scrub_bytes", 0), None, rep, 64]
     assert L.kr_autotune_image(*args(op=5)) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_autotune_image(*args(reps=0)) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_autotune_image(*args(reps=1001)) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_autotune_image(*args(c=1)) == kr.ERR_UNSUPPORTED
     assert L.kr_autotune_image(*args(op=1, flags=4)) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_image(*args(scrub=A + 8, scrub_bytes=1 << 20)) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_image(*args(scrub=A, scrub_bytes=16)) == kr.ERR_INVALID_ARGUMENT
     sing = (ctypes.c_double * 6)(1, 2, 0, 2, 4, 0)
     a = args(op=1)
     a[10] = sing
     assert L.kr_autotune_image(*a) == kr.ERR_SINGULAR_MATRIX
     ws = A + 0x10000000
-    assert L.kr_autotune_batch(batch_items(dst_stride=0), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 5, None,
-                               rep, 64) == kr.ERR_INVALID_ARGUMENT
-    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 16, 5, None, rep, 64) \
+    assert L.kr_autotune_batch(batch_items(dst_stride=0), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 5, None, 0,
+                               None, rep, 64) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 16, 5, None, 0, None, rep, 64) \
         == kr.ERR_WORKSPACE_TOO_SMALL
-    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 0, None, rep, 64) \
+    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 0, None, 0, None, rep, 64) \
         == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 5, A + 4, 1 << 20, None,
+                               rep, 64) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_autotune_load(None) == kr.ERR_INVALID_ARGUMENT

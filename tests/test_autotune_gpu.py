@@ -76,7 +76,8 @@ def test_every_image_config_bit_exact(op, out):
 
     default = run()
     d = torch.empty((dh, dw, 3), dtype=dt, device="cuda")
-    say(f"autotune {op} {out}: {kr.autotune_image(op, src, d, m, border=border, reps=3)}")
+    scrub = torch.empty(32 << 20, dtype=torch.uint8, device="cuda") if out == "u8" else None
+    say(f"autotune {op} {out}: {kr.autotune_image(op, src, d, m, border=border, reps=3, scrub=scrub)}")
     torch.cuda.synchronize()
     tuned = d.cpu().numpy()
     if out == "u8":
@@ -113,7 +114,8 @@ def test_every_batch_config_bit_exact(out):
     default = [sp["dst"].cpu().numpy() for sp in specs]
     for sp in specs:
         sp["dst"].zero_()
-    say(f"autotune batch {out}: {kr.autotune_batch(specs, border=kr.REPLICATE, reps=2)}")
+    scrub = torch.empty(32 << 20, dtype=torch.uint8, device="cuda") if out == "f32" else None
+    say(f"autotune batch {out}: {kr.autotune_batch(specs, border=kr.REPLICATE, reps=2, scrub=scrub)}")
     torch.cuda.synchronize()
     for k, sp in enumerate(specs):
         assert np.array_equal(sp["dst"].cpu().numpy(), default[k]), f"tuned batch item {k}"
