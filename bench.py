@@ -109,26 +109,46 @@ def _traffic_from_profiles(kernel: str):
     return ent.get("bytes_per_launch")
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _cpu_baseline_4k(img, m, seconds: float = 10.0):
     """The oracle timed on the host on a bounded sample of the same workload:
-    repeated full steps (4 ops on the 4K image) for about `seconds`."""
+    repeated full steps (4 ops on the 4K image) for about `seconds` on all
+    host threads, then for about a third of that on one thread."""
     import oracle
-    threads = os.cpu_count() or 1
+
+    def run(threads, budget):
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.resize(img, 1080, 1920, "u8", threads=threads)
+            oracle.resize(img, 1080, 1920, "f64", threads=threads)
+            oracle.warp(img, m, 2160, 3840, "u8", threads=threads)
+            oracle.warp(img, m, 2160, 3840, "f64", threads=threads)
+            steps += 1
+            if time.perf_counter() - t0 >= budget:
+                return steps, time.perf_counter() - t0
+
+    # the host threads this process may use (the box's CPU share), not the machine's
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0)) or 1
     px_per_step = 2 * 1080 * 1920 + 2 * 2160 * 3840
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.resize(img, 1080, 1920, "u8", threads=threads)
-        oracle.resize(img, 1080, 1920, "f64", threads=threads)
-        oracle.warp(img, m, 2160, 3840, "u8", threads=threads)
-        oracle.warp(img, m, 2160, 3840, "f64", threads=threads)
-        steps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
+    steps, dt = run(threads, seconds)
+    steps1, dt1 = run(1, seconds / 3.0)
     return {"value": round(steps * px_per_step / dt / 1e9, 6), "unit": "Gpix/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} full steps of the 4K workload (resize u8+f32, warp u8+f32) in {dt:.1f} s"}
+            "sample": f"{steps} full steps of the 4K workload (resize u8+f32, warp u8+f32) in {dt:.1f} s "
+                      f"on {threads} threads",
+            "single_thread_Gpix_s": round(steps1 * px_per_step / dt1 / 1e9, 6),
+            "single_thread_sample": f"{steps1} full steps in {dt1:.1f} s on 1 thread",
+            "cpu_model": _cpu_model()}
 
 
 def _hbm_copy_ceiling(torch, kr, nbytes=1 << 30, reps=20):

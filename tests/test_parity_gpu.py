@@ -183,3 +183,22 @@ def test_repeat_runs_bitwise():
     b = [gpu_resize(img, 517, 911) for _ in range(3)]
     assert all(np.array_equal(a[0], x) for x in a[1:])
     assert all(np.array_equal(b[0], x) for x in b[1:])
+
+
+def test_stored_oracle_digests():
+    """GPU u8 outputs hash to the digests stored from the oracle."""
+    import json
+    import os
+    from tests.golden import make_golden as mg
+    stored = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_digests.json")))
+    small = wl.uniform_u8(480, 640, 3, seed=0)
+    big = wl.mixed_u8(2160, 3840, 3, seed=0)
+    m = wl.random_affine_4k(2160, 3840, 0)
+    got = {
+        "small_resize_u8": gpu_resize(small, 240, 320, "u8", border=REPL),
+        "4k_resize_u8": gpu_resize(big, 1080, 1920, "u8", border=REPL),
+        "4k_warp_u8": gpu_warp(big, m, 2160, 3840, "u8", border=CONST),
+    }
+    for name, a in got.items():
+        say(f"digest {name}")
+        assert mg.digest(a) == stored[name]["sha256"], name
