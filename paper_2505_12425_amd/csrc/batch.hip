@@ -28,7 +28,7 @@ __global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict
 {
     extern __shared__ uint32_t lds[];
     TileSeq seq(blockIdx.x, gridDim.x, ntiles);
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT>(G, e, lds, [&](TiledJob &t, int &tile) {
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT, false>(G, e, lds, [&](TiledJob &t, int &tile) {
         int g;
         if (!seq.take(g))
             return false;
@@ -49,15 +49,9 @@ __global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict
 template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
 static hipError_t launch_group_cfg(const BatchGroup &g, const Epilogue &e, hipStream_t s)
 {
+    // one workgroup per tile (batch configurations have no persistent mode)
     auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 3>;
-    int grid = g.ntiles;
-    if (g.cfg.persistent) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, KT_THREADS, g.lds) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-        grid = persistent_grid(g.ntiles, per_cu);
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.ntiles, e, g.G);
+    hipLaunchKernelGGL(kern, dim3(g.ntiles), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.ntiles, e, g.G);
     return hipGetLastError();
 }
 

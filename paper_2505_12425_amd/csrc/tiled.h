@@ -40,6 +40,8 @@ constexpr int KT_MARGIN = 16;  // LDS dwords kept free on each side of a box row
 struct TiledJob {
     ImageJob j;
     double m2048[6];  // warp inverse map scaled by 2048 (exact), for the u8 path
+    double rden_x;    // resize: 1 / (2 dst_w), rounded (exact quotients by correction)
+    double rden_y;    // resize: 1 / (2 dst_h), rounded
     int op;           // OP_RESIZE or OP_WARP
     int tiles_x;      // output tiles per row
     int ntiles;       // output tiles in the image
@@ -157,6 +159,48 @@ __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t 
 // one row, so each store instruction writes one contiguous run (RGB u8 is
 // packed across lane quads with a DPP exchange).
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// floor(num / den) and the remainder, for |num| < 2^31 and 0 < den < 2^17,
+// from a rounded reciprocal rden of den: num * rden is within 2^-20 of the
+// exact quotient, so the floor is off by at most one and the exact integer
+// remainder corrects it.
+__device__ __forceinline__ int floor_div_r(int num, int den, double rden, int &rem)
+{
+    int q = (int)__builtin_floor((double)num * rden);
+    int r = num - q * den;
+    if (r < 0) {
+        q -= 1;
+        r += den;
+    } else if (r >= den) {
+        q += 1;
+        r -= den;
+    }
+    rem = r;
+    return q;
+}
+
+// Resize axis map (half-pixel centres, exact rational) with the reciprocal of
+// den = 2 n_out: i0 = floor(((2 d + 1) n_in - n_out) / den); w1 =
+// round-half-even(2048 r / den) by the exact integer rule; f = r / den (f32,
+// correctly rounded).
+__device__ __forceinline__ int resize_i0_r(int d, int n_in, int n_out, double rden)
+{
+    int r;
+    return floor_div_r((2 * d + 1) * n_in - n_out, 2 * n_out, rden, r);
+}
+
+__device__ __forceinline__ void resize_axis_r(int d, int n_in, int n_out, double rden, int &i0, int &w1, float &f)
+{
+    const int den = 2 * n_out;
+    int r, r2;
+    i0 = floor_div_r((2 * d + 1) * n_in - n_out, den, rden, r);
+    const int t = 4096 * r + den;  // < 2^28
+    int q = floor_div_r(t, 2 * den, 0.5 * rden, r2);
+    if (r2 == 0 && (q & 1))
+        q -= 1;
+    w1 = q;
+    f = (float)r / (float)den;
+}
 
 // Pack per-channel results (top byte of v[c]) into one pixel dword, byte c =
 // channel c.
@@ -338,55 +382,58 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
     p.ox1 = min(p.ox0 + TW, j.dw) - 1;
     p.oy1 = min(p.oy0 + TH, j.dh) - 1;
     int x0min, x0max, y0min, y0max;
+    // The four bounds come from four independent evaluations: lane q of the
+    // wave computes the q-th one and every lane reads them back (readlane).
+    const int q = lane_id() & 3;
     if constexpr (OP == OP_RESIZE) {
-        x0min = resize_i0(p.ox0, W, j.dw);
-        x0max = resize_i0(p.ox1, W, j.dw);
-        y0min = resize_i0(p.oy0, H, j.dh);
-        y0max = resize_i0(p.oy1, H, j.dh);
+        const int d = q == 0 ? p.ox0 : (q == 1 ? p.ox1 : (q == 2 ? p.oy0 : p.oy1));
+        const int v = q < 2 ? resize_i0_r(d, W, j.dw, t.rden_x) : resize_i0_r(d, H, j.dh, t.rden_y);
+        x0min = __builtin_amdgcn_readlane(v, 0);
+        x0max = __builtin_amdgcn_readlane(v, 1);
+        y0min = __builtin_amdgcn_readlane(v, 2);
+        y0max = __builtin_amdgcn_readlane(v, 3);
         p.inside = x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
         p.by0 = 0;
         p.nslots = 2 * (p.oy1 - p.oy0 + 1);
     } else {
-        // Tap box from the four corners.  fma(A, x, fma(B, y, C)) is monotone in
-        // x and in y separately, and so are the clamp and the rounding, so the
-        // extremes over the tile sit at its corners.  First unclamped, to find
-        // interior tiles (no clamp, no border logic per pixel).
+        // Tap box from the four corners (lane q takes corner q).  fma(A, x,
+        // fma(B, y, C)) is monotone in x and in y separately, and so are the
+        // clamp and the rounding, so the extremes over the tile sit at its
+        // corners.  First unclamped, to find interior tiles (no clamp, no
+        // border logic per pixel).
         const double *m = F32 ? j.inv : t.m2048;
         const double b = F32 ? 1.0e9 : 2.0e9;  // keeps the integer conversion in range
-        x0min = y0min = 0x7fffffff;
-        x0max = y0max = -0x7fffffff;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const double cx = (double)((q & 1) ? p.ox1 : p.ox0), cy = (double)((q & 2) ? p.oy1 : p.oy0);
-            double X = __builtin_fma(m[0], cx, __builtin_fma(m[1], cy, m[2]));
-            double Y = __builtin_fma(m[3], cx, __builtin_fma(m[4], cy, m[5]));
-            X = X < -b ? -b : (X > b ? b : X);
-            Y = Y < -b ? -b : (Y > b ? b : Y);
-            const int ix = F32 ? (int)__builtin_floor(X) : (rne_i32(X) >> 11);
-            const int iy = F32 ? (int)__builtin_floor(Y) : (rne_i32(Y) >> 11);
-            x0min = min(x0min, ix); x0max = max(x0max, ix);
-            y0min = min(y0min, iy); y0max = max(y0max, iy);
+        const double cx = (double)((q & 1) ? p.ox1 : p.ox0), cy = (double)((q & 2) ? p.oy1 : p.oy0);
+        const double X = __builtin_fma(m[0], cx, __builtin_fma(m[1], cy, m[2]));
+        const double Y = __builtin_fma(m[3], cx, __builtin_fma(m[4], cy, m[5]));
+        auto corner_bounds = [&](int ix, int iy) {
+            const int a0 = __builtin_amdgcn_readlane(ix, 0), a1 = __builtin_amdgcn_readlane(ix, 1);
+            const int a2 = __builtin_amdgcn_readlane(ix, 2), a3 = __builtin_amdgcn_readlane(ix, 3);
+            const int b0 = __builtin_amdgcn_readlane(iy, 0), b1 = __builtin_amdgcn_readlane(iy, 1);
+            const int b2 = __builtin_amdgcn_readlane(iy, 2), b3 = __builtin_amdgcn_readlane(iy, 3);
+            x0min = min(min(a0, a1), min(a2, a3));
+            x0max = max(max(a0, a1), max(a2, a3));
+            y0min = min(min(b0, b1), min(b2, b3));
+            y0max = max(max(b0, b1), max(b2, b3));
+        };
+        {
+            const double Xb = X < -b ? -b : (X > b ? b : X);
+            const double Yb = Y < -b ? -b : (Y > b ? b : Y);
+            const int ix = F32 ? (int)__builtin_floor(Xb) : (rne_i32(Xb) >> 11);
+            const int iy = F32 ? (int)__builtin_floor(Yb) : (rne_i32(Yb) >> 11);
+            corner_bounds(ix, iy);
         }
         p.inside = x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
         if (!p.inside) {
-            x0min = y0min = 0x7fffffff;
-            x0max = y0max = -0x7fffffff;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const double cx = (double)((q & 1) ? p.ox1 : p.ox0), cy = (double)((q & 2) ? p.oy1 : p.oy0);
-                const double X = __builtin_fma(m[0], cx, __builtin_fma(m[1], cy, m[2]));
-                const double Y = __builtin_fma(m[3], cx, __builtin_fma(m[4], cy, m[5]));
-                int ix, iy;
-                if (F32) {
-                    ix = (int)__builtin_floor(clamp_plain(X, W));
-                    iy = (int)__builtin_floor(clamp_plain(Y, H));
-                } else {
-                    ix = rne_i32(clamp_scaled(X, W)) >> 11;
-                    iy = rne_i32(clamp_scaled(Y, H)) >> 11;
-                }
-                x0min = min(x0min, ix); x0max = max(x0max, ix);
-                y0min = min(y0min, iy); y0max = max(y0max, iy);
+            int ix, iy;
+            if (F32) {
+                ix = (int)__builtin_floor(clamp_plain(X, W));
+                iy = (int)__builtin_floor(clamp_plain(Y, H));
+            } else {
+                ix = rne_i32(clamp_scaled(X, W)) >> 11;
+                iy = rne_i32(clamp_scaled(Y, H)) >> 11;
             }
+            corner_bounds(ix, iy);
         }
         p.by0 = y0min;
         p.nslots = y0max + 2 - y0min;
@@ -407,7 +454,7 @@ __device__ __forceinline__ int slot_row(const TiledJob &t, const Plan &p, int s)
     const ImageJob &j = t.j;
     int y;
     if constexpr (OP == OP_RESIZE) {
-        y = resize_i0(p.oy0 + (s >> 1), j.sh, j.dh) + (s & 1);
+        y = resize_i0_r(p.oy0 + (s >> 1), j.sh, j.dh, t.rden_y) + (s & 1);
     } else {
         y = p.by0 + s;
     }
@@ -578,11 +625,11 @@ __device__ __forceinline__ void resize_tables(const TiledJob &t, const Plan &p, 
         int i0, w1;
         float f;
         if (i < TW) {
-            resize_axis(min(p.ox0 + i, p.ox1), j.sw, j.dw, i0, w1, f);
+            resize_axis_r(min(p.ox0 + i, p.ox1), j.sw, j.dw, t.rden_x, i0, w1, f);
             tab[i] = (uint32_t)(i0 - p.bx0 + KT_MARGIN);
             tab[TW + i] = F32 ? __builtin_bit_cast(uint32_t, f) : ((uint32_t)(2048 - w1) | ((uint32_t)w1 << 16));
         } else {
-            resize_axis(min(p.oy0 + (i - TW), p.oy1), j.sh, j.dh, i0, w1, f);
+            resize_axis_r(min(p.oy0 + (i - TW), p.oy1), j.sh, j.dh, t.rden_y, i0, w1, f);
             tab[2 * TW + (i - TW)] = (uint32_t)i0;
             tab[2 * TW + TH + (i - TW)] = F32 ? __builtin_bit_cast(uint32_t, f) : (uint32_t)w1;
         }
@@ -988,8 +1035,9 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
 // ------------------------------------------------------------------ tile pipeline
 // Stage -> (edge fill) -> issue the next tile's loads -> compute this tile.
 // The next tile's global loads stay in flight in registers while this tile is
-// interpolated from LDS.
-template <int OP, int C, bool F32, class L, int MAXIT, typename NextJob>
+// interpolated from LDS.  PIPE = false: the workgroup owns exactly one tile
+// (no registers stay reserved for a next tile during the interpolation).
+template <int OP, int C, bool F32, class L, int MAXIT, bool PIPE, typename NextJob>
 __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, uint32_t *lds, NextJob next_job)
 {
     constexpr int TW = L::TW;
@@ -999,6 +1047,27 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
     if (!next_job(t, tile))
         return;
     Plan p = make_plan<OP, TW, TH, F32>(t, tile, G);
+    if constexpr (!PIPE) {
+        if (!p.direct) {
+            Prefetch<C, MAXIT> pf;
+            prefetch<OP, C, MAXIT>(t, p, G, pf);
+            commit<OP, C, MAXIT>(t, p, G, pf, lds);
+        }
+        if constexpr (OP == OP_RESIZE)
+            resize_tables<TW, TH, F32>(t, p, G, lds);
+        __syncthreads();
+        if (needs_edge_fill(t, p, e)) {
+            fill_edge_columns<OP, C>(t, p, G, lds);
+            __syncthreads();
+        }
+        if (p.direct)
+            compute_gather<OP, C, F32, L>(t, p, G, e, lds);
+        else if constexpr (OP == OP_RESIZE)
+            compute_resize<C, F32, L>(t, p, G, e, lds);
+        else
+            compute_warp<C, F32, L>(t, p, G, e, lds);
+        return;
+    }
     Prefetch<C, MAXIT> pf;
     prefetch<OP, C, MAXIT>(t, p, G, pf);
     while (true) {

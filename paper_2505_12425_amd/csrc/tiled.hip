@@ -11,12 +11,14 @@
 
 namespace kr {
 
-template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT>
+// PERS: persistent grid (each workgroup walks several tiles, prefetching the
+// next one); else one workgroup per tile.
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT, bool PERS>
 __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, TileGeom G)
 {
     extern __shared__ uint32_t lds[];
     TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT>(G, e, lds, [&](TiledJob &t, int &tile) {
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT, PERS>(G, e, lds, [&](TiledJob &t, int &tile) {
         if (!seq.take(tile))
             return false;
         t = job;
@@ -72,6 +74,8 @@ TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th)
     t.j = j;
     for (int i = 0; i < 6; i++)
         t.m2048[i] = 2048.0 * j.inv[i];
+    t.rden_x = 1.0 / (2.0 * (double)j.dw);
+    t.rden_y = 1.0 / (2.0 * (double)j.dh);
     t.op = op;
     t.tiles_x = (j.dw + tw - 1) / tw;
     t.ntiles = t.tiles_x * ((j.dh + th - 1) / th);
@@ -130,9 +134,14 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
     fits = lds <= KT_LDS_CAP;
     if (!fits)
         return hipSuccess;
-    auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT>;
-    const int grid = persistent ? persistent_grid(t.ntiles, blocks_per_cu(kern, lds)) : t.ntiles;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
+    if (persistent) {
+        auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, true>;
+        const int grid = persistent_grid(t.ntiles, blocks_per_cu(kern, lds));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
+    } else {
+        auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, false>;
+        hipLaunchKernelGGL(kern, dim3(t.ntiles), dim3(KT_THREADS), lds, s, t, e, G);
+    }
     return hipGetLastError();
 }
 
