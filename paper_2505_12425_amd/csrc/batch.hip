@@ -87,79 +87,127 @@ hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue 
 
 constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's widest box
 
-// Fraction of a group's output pixels whose images' boxes fit the LDS budget
-// under a configuration (the rest take the global-gather path).
-static double lds_coverage(int op, const TileCfg &cfg, const std::vector<ImageJob> &imgs)
+// Primary tile shape of a batch group when the batch class is not tuned:
+// small tiles, so that batches of small outputs still produce many tiles.
+static TileCfg default_batch_cfg(int op, bool f32)
 {
-    const int tw = cfg.txt * cfg.px * cfg.cpt, th = (KT_THREADS / cfg.txt) * cfg.rpt;
-    double tot = 0, fit = 0;
-    for (const ImageJob &j : imgs) {
-        const double px = (double)j.dh * j.dw;
-        tot += px;
-        if (!wants_gather(j, op) && tile_lds_bytes(tile_geom(j, op, tw, th), tw, th) <= KB_LDS_BUDGET)
-            fit += px;
-    }
-    return tot > 0 ? fit / tot : 1.0;
+    (void)op;
+    return f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false};
 }
 
-// Default tile shape of a batch group: small tiles (batches of small outputs
-// still produce many tiles), squarer ones when shrinking rotated warps would
-// not fit their boxes otherwise.
-static TileCfg default_batch_cfg(int op, bool f32, const std::vector<ImageJob> &imgs)
-{
-    std::vector<TileCfg> pref;
-    if (op == OP_WARP)
-        pref = f32 ? std::vector<TileCfg>{{1, 64, 1, 4, false}, {4, 8, 1, 1, false}}
-                   : std::vector<TileCfg>{{4, 16, 1, 1, false}, {4, 8, 1, 1, false}};
-    else
-        pref = {f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false}};
-    TileCfg best = pref[0];
-    double best_cov = -1;
-    for (const TileCfg &c : pref) {
-        const double cov = lds_coverage(op, c, imgs);
-        if (cov >= 0.95)
-            return c;
-        if (cov > best_cov) {
-            best_cov = cov;
-            best = c;
-        }
-    }
-    return best;
-}
+// Secondary tile shape of warps whose boxes do not fit the primary one.
+static const TileCfg KB_SMALL_TILES{4, 8, 1, 1, false};
 
-// Build the host-side job table of one operation group.  Items whose own box
-// would exceed the LDS budget (and large-ratio resizes) run every tile on the
-// global-gather path; the others set the launch-wide LDS geometry.
-void build_group(int op, bool f32, int c, const std::vector<ImageJob> &imgs, BatchGroup &g,
-                 std::vector<TiledJob> &table, const TileCfg *force)
+static int cfg_tw(const TileCfg &c) { return c.txt * c.px * c.cpt; }
+static int cfg_th(const TileCfg &c) { return (KT_THREADS / c.txt) * c.rpt; }
+
+// One group: job table (tile prefix sums) and launch-wide LDS geometry, the
+// largest box among the items that are staged (stage[i]); the others, and
+// every item when gather is set, read their taps from global memory.
+static void build_group(int op, const TileCfg &cfg, bool gather, const std::vector<ImageJob> &imgs,
+                        const std::vector<bool> &stage, BatchGroup &g, std::vector<TiledJob> &table)
 {
     g.op = op;
-    TileCfg tuned;
-    if (force)
-        g.cfg = *force;
-    else if (!imgs.empty() && tune_lookup(tune_key_batch(op, c, f32, imgs), &tuned))
-        g.cfg = tuned;
-    else
-        g.cfg = default_batch_cfg(op, f32, imgs);
-    const int tw = g.cfg.txt * g.cfg.px * g.cfg.cpt;
-    const int th = (KT_THREADS / g.cfg.txt) * g.cfg.rpt;
+    g.cfg = cfg;
+    const int tw = cfg_tw(cfg), th = cfg_th(cfg);
     table.clear();
     g.G = TileGeom{0, 0};
     int first = 0;
-    for (const ImageJob &j : imgs) {
+    for (size_t i = 0; i < imgs.size(); i++) {
+        const ImageJob &j = imgs[i];
         TiledJob t = make_tiled_job(j, op, tw, th);
         t.first_tile = first;
         first += t.ntiles;
         table.push_back(t);
-        const TileGeom Gi = tile_geom(j, op, tw, th);
-        if (wants_gather(j, op) || tile_lds_bytes(Gi, tw, th) > KB_LDS_BUDGET)
+        if (gather || !stage[i])
             continue;
+        const TileGeom Gi = tile_geom(j, op, tw, th);
         g.G.pitch = std::max(g.G.pitch, Gi.pitch);
         g.G.rows = std::max(g.G.rows, Gi.rows);
     }
     g.njobs = (int)table.size();
     g.ntiles = first;
     g.lds = tile_lds_bytes(g.G, tw, th);
+}
+
+static bool fits(const ImageJob &j, int op, const TileCfg &c, size_t budget)
+{
+    return tile_lds_bytes(tile_geom(j, op, cfg_tw(c), cfg_th(c)), cfg_tw(c), cfg_th(c)) <= budget;
+}
+
+// Resizes form one group: their boxes are predictable, and tiles whose box
+// does not fit (large ratios) take the gather path inside the same launch.
+// Warps are split three ways (primary / 32x32 tiles / gather), so that a few
+// strongly shrinking items neither force the gather path on all of their
+// tiles nor raise every workgroup's LDS footprint.
+void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const TileCfg *const force[2], BatchBuild &b)
+{
+    b.groups.clear();
+    b.tables.clear();
+    for (int k = 0; k < 2; k++) {
+        if (imgs[k].empty())
+            continue;
+        const int op = k == 0 ? OP_RESIZE : OP_WARP;
+        TileCfg P, tuned;
+        if (force[k])
+            P = *force[k];
+        else if (tune_lookup(tune_key_batch(op, c, f32, imgs[k]), &tuned))
+            P = tuned;
+        else
+            P = default_batch_cfg(op, f32);
+        if (op == OP_RESIZE) {
+            std::vector<bool> stage;
+            for (const ImageJob &j : imgs[k])
+                stage.push_back(!wants_gather(j, op) && fits(j, op, P, KB_LDS_BUDGET));
+            b.groups.emplace_back();
+            b.tables.emplace_back();
+            build_group(op, P, false, imgs[k], stage, b.groups.back(), b.tables.back());
+            continue;
+        }
+        std::vector<ImageJob> cls[3];  // primary, small tiles, gather
+        for (const ImageJob &j : imgs[k]) {
+            if (fits(j, op, P, KB_LDS_BUDGET))
+                cls[0].push_back(j);
+            else if (fits(j, op, KB_SMALL_TILES, KT_LDS_CAP))
+                cls[1].push_back(j);
+            else
+                cls[2].push_back(j);
+        }
+        for (int q = 0; q < 3; q++) {
+            if (cls[q].empty())
+                continue;
+            b.groups.emplace_back();
+            b.tables.emplace_back();
+            build_group(op, q == 1 ? KB_SMALL_TILES : P, q == 2, cls[q], std::vector<bool>(cls[q].size(), true),
+                        b.groups.back(), b.tables.back());
+        }
+    }
+}
+
+size_t BatchBuild::bytes() const
+{
+    size_t n = 0;
+    for (const BatchGroup &g : groups)
+        n += table_bytes(g.njobs);
+    return n;
+}
+
+void BatchBuild::pack(uint8_t *host) const
+{
+    size_t off = 0;
+    for (size_t i = 0; i < groups.size(); i++) {
+        std::memcpy(host + off, tables[i].data(), tables[i].size() * sizeof(TiledJob));
+        off += table_bytes(groups[i].njobs);
+    }
+}
+
+void BatchBuild::bind(void *dev)
+{
+    size_t off = 0;
+    for (BatchGroup &g : groups) {
+        g.jobs_dev = reinterpret_cast<const TiledJob *>(static_cast<uint8_t *>(dev) + off);
+        off += table_bytes(g.njobs);
+    }
 }
 
 }  // namespace kr
@@ -227,13 +275,13 @@ static kr_status check_items(const kr_batch_item *items, int n, int c, kr_dtype 
     return KR_OK;
 }
 
-// Device layout of a batch workspace: the resize group's job table, then the
-// warp group's, each 256-byte aligned.
+// Device layout of a batch workspace: the job tables of the batch's groups,
+// each 256-byte aligned (at most KB_MAX_GROUPS groups over n items).
 size_t kr::table_bytes(int n) { return ((size_t)n * sizeof(TiledJob) + 255) & ~(size_t)255; }
 
 extern "C" {
 
-size_t kr_resize_batch_workspace_size(int n) { return n > 0 ? 2 * table_bytes(n) : 256; }
+size_t kr_resize_batch_workspace_size(int n) { return n > 0 ? table_bytes(n) + KB_MAX_GROUPS * 256 : 256; }
 
 kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t, kr_border border,
                           float border_value, const kr_normalize *norm, void *workspace, size_t workspace_bytes,
@@ -256,24 +304,19 @@ kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src
     const Epilogue e = make_epilogue(c, border, border_value, norm);
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = dst_t == KR_F32;
-    uint8_t *wsb = static_cast<uint8_t *>(workspace);
-    BatchGroup groups[2];
-    std::vector<TiledJob> tables[2];
-    build_group(OP_RESIZE, f32, c, rs, groups[0], tables[0], nullptr);
-    build_group(OP_WARP, f32, c, ws, groups[1], tables[1], nullptr);
-    size_t off = 0;
-    for (int k = 0; k < 2; k++) {
-        if (groups[k].njobs == 0)
-            continue;
-        TiledJob *dev = reinterpret_cast<TiledJob *>(wsb + off);
-        off += table_bytes(groups[k].njobs);
-        // pageable source: the runtime stages it before the call returns
-        hipError_t err = hipMemcpyAsync(dev, tables[k].data(), tables[k].size() * sizeof(TiledJob),
-                                        hipMemcpyHostToDevice, s);
-        if (err != hipSuccess)
-            return fail(KR_ERR_HIP, "work-list upload failed: %s", hipGetErrorString(err));
-        groups[k].jobs_dev = dev;
-        err = launch_group(groups[k], c, dst_t, e, s);
+    const std::vector<ImageJob> imgs[2] = {rs, ws};
+    const TileCfg *const none[2] = {nullptr, nullptr};
+    BatchBuild bb;
+    build_batch(imgs, f32, c, none, bb);
+    std::vector<uint8_t> host(bb.bytes());
+    bb.pack(host.data());
+    // pageable source: the runtime stages it before the call returns
+    hipError_t err = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, s);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "work-list upload failed: %s", hipGetErrorString(err));
+    bb.bind(workspace);
+    for (const BatchGroup &g : bb.groups) {
+        err = launch_group(g, c, dst_t, e, s);
         if (err != hipSuccess)
             return fail(KR_ERR_HIP, "batch launch failed: %s", hipGetErrorString(err));
     }
@@ -325,38 +368,33 @@ kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtyp
     kr_batch_plan *p = new (std::nothrow) kr_batch_plan();
     if (!p)
         return fail(KR_ERR_INVALID_ARGUMENT, "out of host memory");
-    BatchGroup groups[2];
-    std::vector<TiledJob> tables[2];
-    build_group(OP_RESIZE, f32, c, rs, groups[0], tables[0], nullptr);
-    build_group(OP_WARP, f32, c, ws, groups[1], tables[1], nullptr);
-    const size_t bytes = kr_resize_batch_workspace_size(n);
-    hipError_t err = hipMalloc(&p->table, bytes);
+    const std::vector<ImageJob> imgs[2] = {rs, ws};
+    const TileCfg *const none[2] = {nullptr, nullptr};
+    BatchBuild bb;
+    build_batch(imgs, f32, c, none, bb);
+    std::vector<uint8_t> host(bb.bytes());
+    bb.pack(host.data());
+    hipError_t err = hipMalloc(&p->table, host.size());
     if (err != hipSuccess) {
         plan_free(p);
         return fail(KR_ERR_HIP, "plan allocation failed: %s", hipGetErrorString(err));
     }
-    size_t off = 0;
-    for (int k = 0; k < 2; k++) {
-        if (groups[k].njobs == 0)
-            continue;
-        TiledJob *dev = reinterpret_cast<TiledJob *>(static_cast<uint8_t *>(p->table) + off);
-        off += table_bytes(groups[k].njobs);
-        err = hipMemcpy(dev, tables[k].data(), tables[k].size() * sizeof(TiledJob), hipMemcpyHostToDevice);
-        if (err != hipSuccess) {
-            plan_free(p);
-            return fail(KR_ERR_HIP, "plan upload failed: %s", hipGetErrorString(err));
-        }
-        groups[k].jobs_dev = dev;
-        p->ntiles += groups[k].ntiles;
+    err = hipMemcpy(p->table, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        plan_free(p);
+        return fail(KR_ERR_HIP, "plan upload failed: %s", hipGetErrorString(err));
     }
+    bb.bind(p->table);
+    for (const BatchGroup &g : bb.groups)
+        p->ntiles += g.ntiles;
     hipStream_t cs = nullptr;
     err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (err == hipSuccess)
         err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (err == hipSuccess) {
         hipError_t lerr = hipSuccess;
-        for (int k = 0; k < 2 && lerr == hipSuccess; k++)
-            lerr = launch_group(groups[k], c, dst_t, e, cs);
+        for (size_t k = 0; k < bb.groups.size() && lerr == hipSuccess; k++)
+            lerr = launch_group(bb.groups[k], c, dst_t, e, cs);
         err = hipStreamEndCapture(cs, &p->graph);
         if (err == hipSuccess)
             err = lerr;
@@ -428,22 +466,34 @@ extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c,
         TileCfg best{};
         float best_ms = -1;
         for (const TileCfg &cfg : batch_candidates(op)) {
-            BatchGroup g;
-            std::vector<TiledJob> table;
-            build_group(op, f32, c, imgs[k], g, table, &cfg);
-            if (g.lds > KT_LDS_CAP)
+            std::vector<ImageJob> only[2];
+            only[k] = imgs[k];
+            const TileCfg *force[2] = {nullptr, nullptr};
+            force[k] = &cfg;
+            BatchBuild bb;
+            build_batch(only, f32, c, force, bb);
+            bool fits = true;
+            for (const BatchGroup &g : bb.groups)
+                fits = fits && g.lds <= KT_LDS_CAP;
+            if (!fits)
                 continue;
-            TiledJob *dev = static_cast<TiledJob *>(workspace);
-            // the host table must outlive the copy: time_launches synchronises the stream
-            hipError_t err = hipMemcpyAsync(dev, table.data(), table.size() * sizeof(TiledJob),
-                                            hipMemcpyHostToDevice, s);
-            g.jobs_dev = dev;
+            std::vector<uint8_t> host(bb.bytes());
+            bb.pack(host.data());
+            // the host image must outlive the copy: time_launches synchronises the stream
+            hipError_t err = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, s);
+            bb.bind(workspace);
+            auto launch_all = [&]() {
+                hipError_t e2 = hipSuccess;
+                for (const BatchGroup &g : bb.groups)
+                    if (e2 == hipSuccess)
+                        e2 = launch_group(g, c, dst_t, e, s);
+                return e2;
+            };
             if (err == hipSuccess)
-                err = launch_group(g, c, dst_t, e, s);  // warm-up
+                err = launch_all();  // warm-up
             float ms = 0;
             if (err == hipSuccess)
-                err = time_launches([&] { return launch_group(g, c, dst_t, e, s); }, reps, scrub, scrub_bytes, s,
-                                    ms);
+                err = time_launches(launch_all, reps, scrub, scrub_bytes, s, ms);
             if (err != hipSuccess) {
                 result = fail(KR_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(err));
                 break;

@@ -20,16 +20,34 @@ struct BatchGroup {
     const TiledJob *jobs_dev = nullptr;  // device copy of the job table
 };
 
-// Host-side job table of one operation group (tile prefix sums, launch-wide
-// LDS geometry).  force: explicit configuration, else the tuned one for this
-// batch class, else the default.
-void build_group(int op, bool f32, int c, const std::vector<ImageJob> &imgs, BatchGroup &g,
-                 std::vector<TiledJob> &table, const TileCfg *force);
+// Every launch of a batch: one group for the resizes; for the warps up to
+// three, by LDS class: boxes that fit the primary tile shape (tuned or
+// default) within the batch LDS budget, boxes that fit 32x32 tiles within the
+// LDS cap, and the rest (global-gather path, no LDS).
+struct BatchBuild {
+    std::vector<BatchGroup> groups;
+    std::vector<std::vector<TiledJob>> tables;
+    // device bytes of all job tables, each 256-byte aligned
+    size_t bytes() const;
+    // the tables concatenated at their device offsets (host staging image)
+    void pack(uint8_t *host) const;
+    // point every group at its table inside a device buffer holding pack()'s image
+    void bind(void *dev);
+};
+
+// Build the launches of a batch (imgs[0]: resizes, imgs[1]: warps).  force[k]:
+// primary configuration of operation k (NULL: tuned for this batch class,
+// else the default).
+void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const TileCfg *const force[2],
+                 BatchBuild &b);
 
 // Launch one group whose job table is already on the device (g.jobs_dev).
 hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue &e, hipStream_t s);
 
-// Bytes of one group's device job table for n images (256-byte multiple).
+// Most groups a batch can have.
+constexpr int KB_MAX_GROUPS = 4;
+
+// Bytes of n job records, 256-byte multiple.
 size_t table_bytes(int n);
 
 }  // namespace kr

@@ -50,24 +50,18 @@ struct HipExec {
                 j.inv[i] = a.req.m[i];
             imgs[a.req.op == OP_WARP ? 1 : 0].push_back(j);
         }
-        BatchGroup groups[2];
-        std::vector<TiledJob> tables[2];
-        size_t off = 0;
-        for (int k = 0; k < 2; k++) {
-            build_group(k == 0 ? OP_RESIZE : OP_WARP, dt == KR_F32, c, imgs[k], groups[k], tables[k], nullptr);
-            if (groups[k].njobs == 0)
-                continue;
-            std::memcpy(static_cast<uint8_t *>(sl.staging) + off, tables[k].data(),
-                        tables[k].size() * sizeof(TiledJob));
-            groups[k].jobs_dev = reinterpret_cast<const TiledJob *>(static_cast<uint8_t *>(sl.table) + off);
-            off += table_bytes(groups[k].njobs);
-        }
-        if (off > table_cap)
+        const TileCfg *const none[2] = {nullptr, nullptr};
+        BatchBuild bb;
+        build_batch(imgs, dt == KR_F32, c, none, bb);
+        const size_t bytes = bb.bytes();
+        if (bytes > table_cap)
             return false;
-        if (hipMemcpyAsync(sl.table, sl.staging, off, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        bb.pack(static_cast<uint8_t *>(sl.staging));
+        if (hipMemcpyAsync(sl.table, sl.staging, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
             return false;
-        for (int k = 0; k < 2; k++)
-            if (launch_group(groups[k], c, dt, e, sl.stream) != hipSuccess)
+        bb.bind(sl.table);
+        for (const BatchGroup &g : bb.groups)
+            if (launch_group(g, c, dt, e, sl.stream) != hipSuccess)
                 return false;
         return hipEventRecord(sl.done, sl.stream) == hipSuccess;
     }
@@ -190,7 +184,7 @@ kr_status kr_server_create(const kr_server_config *cfg, int c, kr_dtype src_t, k
     s->exec.c = c;
     s->exec.dt = dst_t;
     s->exec.e = make_epilogue(c, border, border_value, norm);
-    s->exec.table_cap = 2 * table_bytes(cfg->max_batch);
+    s->exec.table_cap = kr_resize_batch_workspace_size(cfg->max_batch);
     hipError_t err = hipMalloc(&s->arena, cfg->budget_bytes);
     s->exec.arena_base = static_cast<uint8_t *>(s->arena);
     s->exec.slots.resize(cfg->slots);

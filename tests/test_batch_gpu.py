@@ -129,3 +129,36 @@ def test_batch_single_item_and_empty():
     torch.cuda.synchronize()
     assert_u8_equal(dst.cpu().numpy(), oracle.resize(im, 19, 77, "u8"), "single-item batch")
     kr.resize_batch([])  # nothing to do
+
+
+@pytest.mark.parametrize("out", ["u8", "f32"])
+def test_warp_batch_all_lds_classes(out):
+    """Warps whose boxes fit the primary tile shape, only 32x32 tiles, or no
+    tile at all (strong shrinks under rotation: global-gather path) share one
+    batch; every item equals its single call bitwise and the oracle."""
+    rng = np.random.default_rng(21)
+    dt = torch.uint8 if out == "u8" else torch.float32
+    specs, refs = [], []
+    scales = [1.0, 0.9, 0.55, 0.5, 0.3, 0.2, 1.3, 0.25]
+    for i, sc in enumerate(scales):
+        h, w = 700 + 37 * i, 900 + 53 * i
+        im = wl.uniform_u8(h, w, 3, seed=300 + i)
+        m = wl.affine_compose(h, w, 40.0 + 2 * i, sc, 0.1, rng.uniform(-20, 20), rng.uniform(-20, 20))
+        dh, dw = 480 + 16 * i, 640 + 8 * i
+        specs.append({"op": "warp", "src": torch.from_numpy(im).cuda(), "m": m,
+                      "dst": torch.empty((dh, dw, 3), dtype=dt, device="cuda")})
+        refs.append((im, m, dh, dw))
+    say(f"warp batch over LDS classes, out={out}")
+    kr.resize_batch(specs, border=kr.CONSTANT, border_value=9)
+    torch.cuda.synchronize()
+    for i, (sp, (im, m, dh, dw)) in enumerate(zip(specs, refs)):
+        got = sp["dst"].cpu().numpy()
+        single = _single(sp, border=kr.CONSTANT, border_value=9)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy(), got), f"item {i} (scale {scales[i]}): batch != single"
+        if out == "u8":
+            assert_u8_equal(got, oracle.warp(im, m, dh, dw, "u8", border=oracle.CONSTANT, bval=9, threads=TH),
+                            f"item {i}")
+        else:
+            assert_f32_close(got, oracle.warp(im, m, dh, dw, "f64", border=oracle.CONSTANT, bval=9, threads=TH),
+                             f"item {i}")
