@@ -1,4 +1,4 @@
-"""Reference oracle for bilinear resize and affine warp -- TEST INFRASTRUCTURE.
+"""Reference oracle for bilinear / nearest resize and affine warp -- TEST INFRASTRUCTURE.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product library never loads it and
@@ -54,6 +54,8 @@ def _load():
     lib.kro_resize.restype = i
     lib.kro_warp.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, d, dp, dp, i]
     lib.kro_warp.restype = i
+    lib.kro_resize_nearest.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, dp, i]
+    lib.kro_resize_nearest.restype = i
     lib.kro_invert_affine.argtypes = [dp, dp]
     lib.kro_invert_affine.restype = i
     _lib = lib
@@ -101,6 +103,26 @@ def resize(src: np.ndarray, dh: int, dw: int, out: str = "u8", border: int = REP
                         border, float(bval), m, s, threads)
     if rc != 0:
         raise ValueError("kro_resize rejected its arguments")
+    return dst
+
+
+def resize_nearest(src: np.ndarray, dh: int, dw: int, out: str = "u8", mean=None, std=None,
+                   threads: int = 1) -> np.ndarray:
+    """Oracle nearest-neighbour resize (half-pixel centres).  ``out`` is "u8"
+    (u8 sources: the copied samples) or "f64" (the f32 path's values)."""
+    lib = _load()
+    src, st = _src_args(src)
+    h, w, c = src.shape
+    if out == "u8":
+        dst = np.zeros((dh, dw, c), np.uint8)
+        ot = 0
+    else:
+        dst = np.zeros((dh, dw, c), np.float64)
+        ot = 1
+    m, s, _keep = _norm_args(mean, std, c)
+    rc = lib.kro_resize_nearest(src.ctypes.data, h, w, c, st, dst.ctypes.data, dh, dw, ot, m, s, threads)
+    if rc != 0:
+        raise ValueError("kro_resize_nearest rejected its arguments")
     return dst
 
 

@@ -1,5 +1,5 @@
 /*
- * kro.c -- reference oracle for bilinear resize and affine warp (TEST
+ * kro.c -- reference oracle for bilinear / nearest resize and affine warp (TEST
  * INFRASTRUCTURE ONLY).
  *
  * This file is the plain, slow, obviously-correct CPU definition that the HIP
@@ -32,6 +32,9 @@
  *  - f32 output: the same taps with unquantised binary64 weights (1 - f, f),
  *    on the 0..255 scale; optionally normalised per channel as
  *    (v / 255 - mean_c) / std_c.  The oracle reports these values in binary64.
+ *
+ * Nearest-neighbour resize (kro_resize_nearest) takes the sample at
+ * floor((d + 1/2) * n_in / n_out) per axis, an exact integer quotient.
  *
  * Parity status: every function here is pinned by the tests in
  * tests/test_oracle.py (closed forms, exact permutations, an exact-rational
@@ -156,6 +159,46 @@ int kro_resize(const void *src, int sh, int sw, int c, int src_t,
                         x0, y0, weight_from_ratio(rx, denx), weight_from_ratio(ry, deny),
                         (double)rx / (double)denx, (double)ry / (double)deny,
                         border, bval, mean, stdv);
+        }
+    }
+    return 0;
+}
+
+/* Nearest-neighbour resize with half-pixel centres (the paper's other
+ * benchmarked resize, Sec. III): output pixel dx takes source column
+ * floor((dx + 1/2) * W_in / W_out) = floor((2 dx + 1) W_in / (2 W_out)), an
+ * exact integer quotient of non-negative integers that never exceeds
+ * W_in - 1; rows likewise.  u8 output (u8 sources only) copies the sample;
+ * f64 output is the sample value, optionally normalised per channel as
+ * (v / 255 - mean_c) / std_c.  Returns 0, or -1 on bad arguments. */
+int kro_resize_nearest(const void *src, int sh, int sw, int c, int src_t,
+                       void *dst, int dh, int dw, int out_t,
+                       const double *mean, const double *stdv, int nthreads)
+{
+    if (sh < 1 || sw < 1 || dh < 1 || dw < 1 || c < 1 || c > 4)
+        return -1;
+    if (out_t == KRO_OUT_U8 && src_t != KRO_U8)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int dy = 0; dy < dh; dy++) {
+        int64_t sy = ((int64_t)(2 * dy + 1) * sh) / (2 * (int64_t)dh);
+        for (int dx = 0; dx < dw; dx++) {
+            int64_t sx = ((int64_t)(2 * dx + 1) * sw) / (2 * (int64_t)dw);
+            size_t sidx = ((size_t)sy * (size_t)sw + (size_t)sx) * (size_t)c;
+            size_t didx = ((size_t)dy * (size_t)dw + (size_t)dx) * (size_t)c;
+            for (int ch = 0; ch < c; ch++) {
+                if (out_t == KRO_OUT_U8) {
+                    ((uint8_t *)dst)[didx + (size_t)ch] = ((const uint8_t *)src)[sidx + (size_t)ch];
+                } else {
+                    double v = src_t == KRO_U8 ? (double)((const uint8_t *)src)[sidx + (size_t)ch]
+                                               : (double)((const float *)src)[sidx + (size_t)ch];
+                    if (mean && stdv)
+                        v = (v / 255.0 - mean[ch]) / stdv[ch];
+                    ((double *)dst)[didx + (size_t)ch] = v;
+                }
+            }
         }
     }
     return 0;

@@ -96,3 +96,23 @@ def warp(src: np.ndarray, m, dh: int, dw: int, out="u8", inverse=False, border=0
             x0, y0 = math.floor(fxs), math.floor(fys)
             dst[y, x, :] = _blend(src, x0, y0, fxs - x0, fys - y0, out, border, bval, mean, std)
     return dst
+
+
+def resize_nearest(src: np.ndarray, dh: int, dw: int, out="u8", mean=None, std=None):
+    """Nearest neighbour with half-pixel centres, from the definition: the
+    sample whose cell contains the output centre, source coordinate
+    (d + 1/2) * n_in / n_out as an exact Fraction, then its floor."""
+    h, w, c = src.shape
+    res = np.zeros((dh, dw, c), np.uint8 if out == "u8" else np.float64)
+    for dy in range(dh):
+        sy = math.floor((Fraction(dy) + Fraction(1, 2)) * Fraction(h, dh))
+        for dx in range(dw):
+            sx = math.floor((Fraction(dx) + Fraction(1, 2)) * Fraction(w, dw))
+            for ch in range(c):
+                v = src[sy, sx, ch]
+                if out == "u8":
+                    res[dy, dx, ch] = v
+                else:
+                    v = float(v)
+                    res[dy, dx, ch] = (v / 255.0 - mean[ch]) / std[ch] if mean is not None else v
+    return res

@@ -360,3 +360,46 @@ def test_warp_uses_fused_multiply_add(axis):
     fused = bf.fma(big, 5.0, c)
     unfused = big * 5.0 + c
     assert round(2048 * (fused % 1.0)) != round(2048 * (unfused % 1.0))
+
+
+# ---------------------------------------------------------------- nearest neighbour
+def test_nearest_identity_is_a_copy():
+    img = wl.uniform_u8(23, 31, 3, seed=5)
+    assert np.array_equal(oracle.resize_nearest(img, 23, 31), img)
+    imgf = wl.uniform_f32(9, 12, 2, seed=6)
+    assert np.array_equal(oracle.resize_nearest(imgf, 9, 12, "f64"), imgf.astype(np.float64))
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_nearest_integer_upscale_replicates(k):
+    img = wl.uniform_u8(7, 9, 3, seed=k)
+    exp = np.repeat(np.repeat(img, k, axis=0), k, axis=1)
+    assert np.array_equal(oracle.resize_nearest(img, 7 * k, 9 * k), exp)
+
+
+def test_nearest_exact_downscale_takes_cell_centres():
+    img = wl.uniform_u8(24, 36, 3, seed=9)
+    # 2x: the centre of output cell d lies on the edge between source 2d and
+    # 2d + 1; half-pixel rounding takes 2d + 1.  3x: the middle sample 3d + 1.
+    assert np.array_equal(oracle.resize_nearest(img, 12, 18), img[1::2, 1::2])
+    assert np.array_equal(oracle.resize_nearest(img, 8, 12), img[1::3, 1::3])
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 5, 3), (6, 10, 13, 7), (11, 4, 3, 9), (1, 1, 4, 6), (9, 13, 1, 1)])
+def test_nearest_matches_bruteforce(shape):
+    h, w, dh, dw = shape
+    img = wl.uniform_u8(h, w, 3, seed=h * w)
+    assert np.array_equal(oracle.resize_nearest(img, dh, dw), bf.resize_nearest(img, dh, dw))
+    mean, std = wl.IMAGENET_MEAN, wl.IMAGENET_STD
+    got = oracle.resize_nearest(img, dh, dw, "f64", mean, std)
+    assert np.allclose(got, bf.resize_nearest(img, dh, dw, "f64", mean, std), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(40, 60, 17, 23), (17, 23, 40, 60), (480, 640, 240, 320), (33, 35, 100, 7)])
+def test_nearest_matches_torch_nearest_exact(shape):
+    h, w, dh, dw = shape
+    img = wl.uniform_u8(h, w, 3, seed=h + 3 * w)
+    t = torch.from_numpy(img.astype(np.float64)).permute(2, 0, 1)[None]
+    ref = torch.nn.functional.interpolate(t, size=(dh, dw), mode="nearest-exact")[0].permute(1, 2, 0).numpy()
+    assert np.array_equal(oracle.resize_nearest(img, dh, dw, "f64"), ref)
+    assert np.array_equal(oracle.resize_nearest(img, dh, dw), ref.astype(np.uint8))

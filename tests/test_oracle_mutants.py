@@ -36,6 +36,12 @@ MUTANTS = [
     ("normalise order", "v = (v / 255.0 - mean[ch]) / stdv[ch];", "v = (v - mean[ch]) / stdv[ch] / 255.0;"),
     ("swapped inverse terms", "double A = m[4] / det, B = -m[1] / det, D = -m[3] / det, E = m[0] / det;",
      "double A = m[4] / det, B = -m[3] / det, D = -m[1] / det, E = m[0] / det;"),
+    ("nearest without half-pixel", "int64_t sx = ((int64_t)(2 * dx + 1) * sw) / (2 * (int64_t)dw);",
+     "int64_t sx = ((int64_t)(2 * dx) * sw) / (2 * (int64_t)dw);"),
+    ("nearest row scale from columns", "int64_t sy = ((int64_t)(2 * dy + 1) * sh) / (2 * (int64_t)dh);",
+     "int64_t sy = ((int64_t)(2 * dy + 1) * sh) / (2 * (int64_t)dw);"),
+    ("nearest rounds up", "int64_t sx = ((int64_t)(2 * dx + 1) * sw) / (2 * (int64_t)dw);",
+     "int64_t sx = ((int64_t)(2 * dx + 1) * sw + 2 * (int64_t)dw - 1) / (2 * (int64_t)dw); if (sx >= sw) sx = sw - 1;"),
     ("wrong tap row (f64)", "+ fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0 + 1, ch, border, bval);",
      "+ fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0, ch, border, bval);"),
 ]
