@@ -15,7 +15,8 @@ the 256 MB Infinity Cache holds) so that every step reads its source from HBM.
 Other workloads: --workload batch (256 mixed-size images -> 224x224 f32
 normalised, one persistent launch, vs per-image launches), --workload warpbatch
 (64 x 1080p warps, graph replay, vs per-image launches), --workload serve
-(continuous-batching request stream; p50/p99 latency).
+(continuous-batching request stream; p50/p99 latency), --workload nearest
+(nearest-neighbour resize 4K <-> 1080p).
 
 Prints ONE JSON line.  Kernel durations come from HIP events recorded around
 every launch on the launch stream; the roofline entry uses the kernel with the
@@ -67,6 +68,16 @@ def resize_touched_bytes(h, w, dh, dw, c=3, esize=1) -> int:
     ys, xs = taps(h, dh), taps(w, dw)
     mask = np.zeros((h, w), bool)
     mask[np.ix_(ys, xs)] = True
+    return _lines_of_pixel_mask(mask, c, esize)
+
+
+def nearest_touched_bytes(h, w, dh, dw, c=3, esize=1) -> int:
+    """Source bytes (line granular) read by a half-pixel nearest-neighbour resize."""
+    def idx(n_in, n_out):
+        d = np.arange(n_out, dtype=np.int64)
+        return np.unique(((2 * d + 1) * n_in) // (2 * n_out))
+    mask = np.zeros((h, w), bool)
+    mask[np.ix_(idx(h, dh), idx(w, dw))] = True
     return _lines_of_pixel_mask(mask, c, esize)
 
 
@@ -388,6 +399,51 @@ def bench_warpbatch(args, torch, kr, wl):
     }
 
 
+# ---------------------------------------------------------------- nearest neighbour
+def bench_nearest(args, torch, kr, wl):
+    """Nearest-neighbour resize 4K <-> 1080p, u8 and f32 outputs: per-kernel
+    duration (back to back, rotating cold sources) and HBM roofline."""
+    cases = [("down_u8", (2160, 3840), (1080, 1920), torch.uint8), ("down_f32", (2160, 3840), (1080, 1920), torch.float32),
+             ("up_u8", (1080, 1920), (2160, 3840), torch.uint8), ("up_f32", (1080, 1920), (2160, 3840), torch.float32)]
+    copies = args.cold_copies
+    kern, total_px, total_ms = {}, 0, 0.0
+    for name, (h, w), (dh, dw), dt in cases:
+        img = wl.mixed_u8(h, w, 3, seed=0)
+        srcs = [torch.from_numpy(img).cuda() for _ in range(copies)]
+        out = torch.empty((dh, dw, 3), dtype=dt, device="cuda")
+        for i in range(args.warmup):
+            kr.resize_nearest(srcs[i % copies], out)
+        reps = max(args.steps, 20)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for i in range(reps):
+            kr.resize_nearest(srcs[i % copies], out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        alg = nearest_touched_bytes(h, w, dh, dw) + dh * dw * 3 * (1 if dt == torch.uint8 else 4)
+        gbps = alg / (ms * 1e-3) / 1e9
+        kern[name] = {"avg_us": round(ms * 1e3, 3), "alg_bytes": alg, "GBps": round(gbps, 1),
+                      "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(dh * dw / (ms * 1e-3) / 1e9, 2),
+                      "traffic": _traffic_from_profiles("nearest_" + name)}
+        total_px += dh * dw
+        total_ms += ms
+        del srcs
+    dom = max(kern, key=lambda n: kern[n]["avg_us"])
+    k = kern[dom]
+    return {
+        "metric": "output Gpixels/s (nearest-neighbour resize 4K -> 1080p and 1080p -> 4K, u8 and f32 outputs)",
+        "value": round(total_px / (total_ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(total_ms, 4),
+        "config": {"workload": "nearest: 3840x2160x3 u8 -> 1920x1080 and 1920x1080x3 u8 -> 3840x2160, "
+                               "half-pixel centres, u8 and f32 outputs, cold sources", "px_per_step": total_px},
+        "roofline": {"bound": "hbm", "kernel": "nearest_" + dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": k["frac"], "traffic": k["traffic"], "alg_bytes_per_launch": k["alg_bytes"],
+                     "avg_launch_us": k["avg_us"]},
+        "kernels": kern,
+    }
+
+
 # ---------------------------------------------------------------- serving
 def bench_serve(args, torch, kr, wl):
     """10,000 requests (70 % resize, 30 % warp) with Poisson arrivals, sources
@@ -452,7 +508,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve"])
+    ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve", "nearest"])
     ap.add_argument("--cold-copies", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "file", "live", "off"],
@@ -488,7 +544,8 @@ def main():
     # the copy ceiling (also the calibration point of HBM byte counters)
     copy_gbps = _hbm_copy_ceiling(torch, kr)
     if args.workload != "4k":
-        fn = {"batch": bench_batch, "warpbatch": bench_warpbatch, "serve": bench_serve}[args.workload]
+        fn = {"batch": bench_batch, "warpbatch": bench_warpbatch, "serve": bench_serve,
+              "nearest": bench_nearest}[args.workload]
         r = fn(args, torch, kr, wl)
         out = {"metric": r.pop("metric"), "value": r.pop("value"), "unit": r.pop("unit")}
         out.update(common)

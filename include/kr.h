@@ -88,6 +88,18 @@ kr_status kr_resize_bilinear(const void *src, int src_h, int src_w, int c, kr_dt
                              void *stream);
 
 /*
+ * Nearest-neighbour resize of one image (the paper's other benchmarked
+ * resize, Sec. III): output pixel (x, y) copies the source sample at column
+ * floor((x + 1/2) * src_w / dst_w) and row floor((y + 1/2) * src_h / dst_h),
+ * exact integer quotients (never outside the source, so no border rule).
+ * Same arguments and type pairs as kr_resize_bilinear without the border;
+ * an F32 destination takes v * 1 or the normalisation of norm.
+ */
+kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dtype src_t,
+                            void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                            const kr_normalize *norm, void *stream);
+
+/*
  * Bilinear affine warp of one image (Sec. II-A geometric transforms).
  * m: HOST pointer to the row-major 2x3 matrix [[a, b, c], [d, e, f]].  It
  * maps source to destination unless flags contains KR_WARP_INVERSE_MAP.  A

@@ -184,6 +184,24 @@ kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype 
     return KR_OK;
 }
 
+kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst, int dst_h,
+                            int dst_w, kr_dtype dst_t, const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, KR_BORDER_REPLICATE, 0.0f,
+                               norm);
+    if (s != KR_OK)
+        return s;
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    const Epilogue e = make_epilogue(c, KR_BORDER_REPLICATE, 0.0f, norm);
+    const hipError_t err = launch_nearest(c, src_t, dst_t, j, e, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "nearest resize launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
 kr_status kr_invert_affine(const double m[6], double inv[6])
 {
     clear_error();

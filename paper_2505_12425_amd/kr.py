@@ -67,6 +67,8 @@ def lib():
     L.kr_resize_bilinear.restype = i
     L.kr_warp_affine.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
     L.kr_warp_affine.restype = i
+    L.kr_resize_nearest.argtypes = [vp, i, i, i, i, vp, i, i, i, npp, vp]
+    L.kr_resize_nearest.restype = i
     L.kr_invert_affine.argtypes = [dp, dp]
     L.kr_invert_affine.restype = i
     L.kr_status_string.argtypes = [i]
@@ -170,6 +172,15 @@ def resize(src, dst, border: int = REPLICATE, border_value: float = 0.0, mean=No
         raise ValueError("src and dst channel counts differ")
     check(lib().kr_resize_bilinear(sp, sh, sw, c, st, dp_, dh, dw, dt, border, float(border_value),
                                    _normalize(mean, std, c), _stream(stream)))
+
+
+def resize_nearest(src, dst, mean=None, std=None, stream=None) -> None:
+    """kr_resize_nearest on torch tensors: src HWC -> dst HWC (its size is the target)."""
+    sp, sh, sw, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if dc != c:
+        raise ValueError("src and dst channel counts differ")
+    check(lib().kr_resize_nearest(sp, sh, sw, c, st, dp_, dh, dw, dt, _normalize(mean, std, c), _stream(stream)))
 
 
 def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, border_value: float = 0.0,

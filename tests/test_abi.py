@@ -259,3 +259,16 @@ def test_autotune_validation():
     assert L.kr_autotune_batch(batch_items(), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, 5, A + 4, 1 << 20, None,
                                rep, 64) == kr.ERR_INVALID_ARGUMENT
     assert L.kr_autotune_load(None) == kr.ERR_INVALID_ARGUMENT
+
+
+def test_nearest_validation():
+    L = kr.lib()
+    f = L.kr_resize_nearest
+    assert f(None, 480, 640, 3, kr.U8, B, 240, 320, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT
+    assert f(A, 0, 640, 3, kr.U8, B, 240, 320, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT
+    assert f(A, 480, 640, 3, kr.U8, B, 240, 40000, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT
+    assert f(A, 480, 640, 5, kr.U8, B, 240, 320, kr.U8, None, None) == kr.ERR_UNSUPPORTED
+    assert f(A, 480, 640, 3, kr.F32, B, 240, 320, kr.U8, None, None) == kr.ERR_UNSUPPORTED
+    assert f(A, 480, 640, 3, kr.U8, B, 240, 320, kr.U8, norm_ptr(), None) == kr.ERR_INVALID_ARGUMENT
+    assert f(A, 480, 640, 3, kr.U8, A + 64, 240, 320, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT  # overlap
+    assert f(A + 4, 480, 640, 3, kr.U8, B, 240, 320, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT  # misaligned
