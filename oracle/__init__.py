@@ -56,6 +56,10 @@ def _load():
     lib.kro_warp.restype = i
     lib.kro_resize_nearest.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, dp, i]
     lib.kro_resize_nearest.restype = i
+    lib.kro_flip.argtypes = [vp, i, i, i, i, vp, i, i]
+    lib.kro_flip.restype = i
+    lib.kro_rgb_to_gray.argtypes = [vp, i, i, i, vp, i, dp, dp, i]
+    lib.kro_rgb_to_gray.restype = i
     lib.kro_invert_affine.argtypes = [dp, dp]
     lib.kro_invert_affine.restype = i
     _lib = lib
@@ -123,6 +127,32 @@ def resize_nearest(src: np.ndarray, dh: int, dw: int, out: str = "u8", mean=None
     rc = lib.kro_resize_nearest(src.ctypes.data, h, w, c, st, dst.ctypes.data, dh, dw, ot, m, s, threads)
     if rc != 0:
         raise ValueError("kro_resize_nearest rejected its arguments")
+    return dst
+
+
+def flip(src: np.ndarray, flip_x: bool = True, flip_y: bool = False) -> np.ndarray:
+    """Oracle flip: mirrors columns (flip_x) and/or rows (flip_y); same dtype."""
+    lib = _load()
+    src, st = _src_args(src)
+    h, w, c = src.shape
+    dst = np.zeros_like(src)
+    if lib.kro_flip(src.ctypes.data, h, w, c, st, dst.ctypes.data, int(flip_x), int(flip_y)) != 0:
+        raise ValueError("kro_flip rejected its arguments")
+    return dst
+
+
+def rgb_to_gray(src: np.ndarray, out: str = "u8", mean=None, std=None, threads: int = 1) -> np.ndarray:
+    """Oracle RGB -> gray (BT.601): HxWx3 -> HxWx1, "u8" (14-bit fixed point)
+    or "f64"."""
+    lib = _load()
+    src, st = _src_args(src)
+    h, w, c = src.shape
+    if c != 3:
+        raise ValueError("rgb_to_gray needs 3 channels")
+    dst = np.zeros((h, w, 1), np.uint8 if out == "u8" else np.float64)
+    m, s, _keep = _norm_args(mean, std, 1)
+    if lib.kro_rgb_to_gray(src.ctypes.data, h, w, st, dst.ctypes.data, 0 if out == "u8" else 1, m, s, threads) != 0:
+        raise ValueError("kro_rgb_to_gray rejected its arguments")
     return dst
 
 

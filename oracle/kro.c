@@ -35,6 +35,8 @@
  *
  * Nearest-neighbour resize (kro_resize_nearest) takes the sample at
  * floor((d + 1/2) * n_in / n_out) per axis, an exact integer quotient.
+ * Flip (kro_flip) mirrors the pixel order; RGB to gray (kro_rgb_to_gray)
+ * uses BT.601 luma weights (14-bit fixed point for u8 output).
  *
  * Parity status: every function here is pinned by the tests in
  * tests/test_oracle.py (closed forms, exact permutations, an exact-rational
@@ -199,6 +201,66 @@ int kro_resize_nearest(const void *src, int sh, int sw, int c, int src_t,
                     ((double *)dst)[didx + (size_t)ch] = v;
                 }
             }
+        }
+    }
+    return 0;
+}
+
+/* Flip (Sec. III "horizontal flip"): out(x, y) = in(flip_x ? W-1-x : x,
+ * flip_y ? H-1-y : y), every channel, same sample type (1 byte or 4). */
+int kro_flip(const void *src, int h, int w, int c, int src_t, void *dst, int flip_x, int flip_y)
+{
+    if (h < 1 || w < 1 || c < 1 || c > 4)
+        return -1;
+    const size_t es = src_t == KRO_U8 ? 1 : 4;
+    for (int y = 0; y < h; y++) {
+        int sy = flip_y ? h - 1 - y : y;
+        for (int x = 0; x < w; x++) {
+            int sx = flip_x ? w - 1 - x : x;
+            const uint8_t *s = (const uint8_t *)src + ((size_t)sy * w + sx) * c * es;
+            uint8_t *d = (uint8_t *)dst + ((size_t)y * w + x) * c * es;
+            for (size_t b = 0; b < (size_t)c * es; b++)
+                d[b] = s[b];
+        }
+    }
+    return 0;
+}
+
+/* RGB to gray (Sec. III "RGB to grayscale"), ITU-R BT.601 luma weights.
+ * u8 output (u8 sources): OpenCV-style 14-bit fixed point,
+ * (4899 R + 9617 G + 1868 B + 2^13) >> 14 (weights sum to 2^14, so a grey
+ * pixel keeps its value).  f64 output: 0.299 R + 0.587 G + 0.114 B on the
+ * sample scale, optionally normalised as (v / 255 - mean) / std. */
+int kro_rgb_to_gray(const void *src, int h, int w, int src_t, void *dst, int out_t,
+                    const double *mean, const double *stdv, int nthreads)
+{
+    if (h < 1 || w < 1)
+        return -1;
+    if (out_t == KRO_OUT_U8 && src_t != KRO_U8)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int y = 0; y < h; y++) {
+        for (int x = 0; x < w; x++) {
+            size_t i = (size_t)y * w + x;
+            double r, g, b;
+            if (src_t == KRO_U8) {
+                const uint8_t *p = (const uint8_t *)src + 3 * i;
+                if (out_t == KRO_OUT_U8) {
+                    int64_t acc = 4899 * (int64_t)p[0] + 9617 * (int64_t)p[1] + 1868 * (int64_t)p[2];
+                    ((uint8_t *)dst)[i] = (uint8_t)((acc + (1 << 13)) >> 14);
+                    continue;
+                }
+                r = p[0]; g = p[1]; b = p[2];
+            } else {
+                const float *p = (const float *)src + 3 * i;
+                r = p[0]; g = p[1]; b = p[2];
+            }
+            double v = 0.299 * r + 0.587 * g + 0.114 * b;
+            if (mean && stdv)
+                v = (v / 255.0 - mean[0]) / stdv[0];
+            ((double *)dst)[i] = v;
         }
     }
     return 0;

@@ -403,3 +403,46 @@ def test_nearest_matches_torch_nearest_exact(shape):
     ref = torch.nn.functional.interpolate(t, size=(dh, dw), mode="nearest-exact")[0].permute(1, 2, 0).numpy()
     assert np.array_equal(oracle.resize_nearest(img, dh, dw, "f64"), ref)
     assert np.array_equal(oracle.resize_nearest(img, dh, dw), ref.astype(np.uint8))
+
+
+# ---------------------------------------------------------------- flip, RGB -> gray
+@pytest.mark.parametrize("c", [1, 3, 4])
+def test_flip_matches_numpy(c):
+    img = wl.uniform_u8(13, 17, c, seed=c)
+    assert np.array_equal(oracle.flip(img, True, False), img[:, ::-1])
+    assert np.array_equal(oracle.flip(img, False, True), img[::-1])
+    assert np.array_equal(oracle.flip(img, True, True), img[::-1, ::-1])
+    assert np.array_equal(oracle.flip(img, False, False), img)
+    f = wl.uniform_f32(9, 6, c, seed=c)
+    assert np.array_equal(oracle.flip(f, True, False), f[:, ::-1])
+
+
+def test_flip_equals_mirror_warp():
+    img = wl.uniform_u8(19, 23, 3, seed=2)
+    m = np.array([[-1.0, 0.0, 22.0], [0.0, 1.0, 0.0]])
+    assert np.array_equal(oracle.flip(img, True, False), oracle.warp(img, m, 19, 23, "u8"))
+
+
+def test_gray_u8_closed_forms():
+    v = np.arange(256, dtype=np.uint8)
+    grey = np.stack([v, v, v], axis=-1)[None]
+    assert np.array_equal(oracle.rgb_to_gray(grey)[0, :, 0], v)  # weights sum to 2^14
+    prim = np.array([[[255, 0, 0], [0, 255, 0], [0, 0, 255], [255, 255, 0]]], np.uint8)
+    exp = [(4899 * 255 + 8192) >> 14, (9617 * 255 + 8192) >> 14, (1868 * 255 + 8192) >> 14,
+           ((4899 + 9617) * 255 + 8192) >> 14]
+    assert oracle.rgb_to_gray(prim)[0, :, 0].tolist() == exp == [76, 150, 29, 226]
+
+
+def test_gray_matches_integer_and_float_definitions():
+    img = wl.uniform_u8(31, 47, 3, seed=4)
+    p = img.astype(np.int64)
+    exp = (4899 * p[..., 0] + 9617 * p[..., 1] + 1868 * p[..., 2] + 8192) >> 14
+    assert np.array_equal(oracle.rgb_to_gray(img)[..., 0], exp.astype(np.uint8))
+    f = oracle.rgb_to_gray(img, "f64")[..., 0]
+    q = img.astype(np.float64)
+    assert np.allclose(f, q @ np.array([0.299, 0.587, 0.114]), rtol=0, atol=1e-12)
+    fn = oracle.rgb_to_gray(img, "f64", [0.45], [0.25])[..., 0]
+    assert np.allclose(fn, (f / 255.0 - 0.45) / 0.25, rtol=0, atol=1e-12)
+    src = wl.uniform_f32(5, 8, 3, seed=1)
+    g = oracle.rgb_to_gray(src, "f64")[..., 0]
+    assert np.allclose(g, src.astype(np.float64) @ np.array([0.299, 0.587, 0.114]), rtol=0, atol=1e-9)

@@ -42,6 +42,10 @@ MUTANTS = [
      "int64_t sy = ((int64_t)(2 * dy + 1) * sh) / (2 * (int64_t)dw);"),
     ("nearest rounds up", "int64_t sx = ((int64_t)(2 * dx + 1) * sw) / (2 * (int64_t)dw);",
      "int64_t sx = ((int64_t)(2 * dx + 1) * sw + 2 * (int64_t)dw - 1) / (2 * (int64_t)dw); if (sx >= sw) sx = sw - 1;"),
+    ("gray R/B weights swapped", "4899 * (int64_t)p[0] + 9617 * (int64_t)p[1] + 1868 * (int64_t)p[2]",
+     "1868 * (int64_t)p[0] + 9617 * (int64_t)p[1] + 4899 * (int64_t)p[2]"),
+    ("gray truncation", "((acc + (1 << 13)) >> 14)", "(acc >> 14)"),
+    ("flip shifted by one", "int sx = flip_x ? w - 1 - x : x;", "int sx = flip_x ? (w - x) % w : x;"),
     ("wrong tap row (f64)", "+ fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0 + 1, ch, border, bval);",
      "+ fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0, ch, border, bval);"),
 ]
