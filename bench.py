@@ -15,8 +15,8 @@ the 256 MB Infinity Cache holds) so that every step reads its source from HBM.
 Other workloads: --workload batch (256 mixed-size images -> 224x224 f32
 normalised, one persistent launch, vs per-image launches), --workload warpbatch
 (64 x 1080p warps, graph replay, vs per-image launches), --workload serve
-(continuous-batching request stream; p50/p99 latency), --workload nearest
-(nearest-neighbour resize 4K <-> 1080p).
+(continuous-batching request stream; p50/p99 latency), --workload ops
+(nearest-neighbour resize 4K <-> 1080p, flip and RGB -> gray at 4K).
 
 Prints ONE JSON line.  Kernel durations come from HIP events recorded around
 every launch on the launch stream; the roofline entry uses the kernel with the
@@ -399,45 +399,80 @@ def bench_warpbatch(args, torch, kr, wl):
     }
 
 
-# ---------------------------------------------------------------- nearest neighbour
-def bench_nearest(args, torch, kr, wl):
-    """Nearest-neighbour resize 4K <-> 1080p, u8 and f32 outputs: per-kernel
-    duration (back to back, rotating cold sources) and HBM roofline."""
-    cases = [("down_u8", (2160, 3840), (1080, 1920), torch.uint8), ("down_f32", (2160, 3840), (1080, 1920), torch.float32),
-             ("up_u8", (1080, 1920), (2160, 3840), torch.uint8), ("up_f32", (1080, 1920), (2160, 3840), torch.float32)]
+# ---------------------------------------------------------------- the other Sec. III operators
+def bench_ops(args, torch, kr, wl):
+    """The paper's other benchmarked per-image operators at 4K: nearest-neighbour
+    resize 4K <-> 1080p, horizontal flip, RGB -> gray; u8 and f32 outputs.
+    Per-kernel duration (back to back, rotating cold sources) and HBM roofline."""
     copies = args.cold_copies
     kern, total_px, total_ms = {}, 0, 0.0
-    for name, (h, w), (dh, dw), dt in cases:
+    big, small = (2160, 3840), (1080, 1920)
+
+    def nearest(dst_hw, dt):
+        def make(src):
+            out = torch.empty(dst_hw + (3,), dtype=dt, device="cuda")
+            return lambda s: kr.resize_nearest(s, out)
+        return make
+
+    def flip(dt):
+        def make(src):
+            out = torch.empty_like(src)
+            return lambda s: kr.flip(s, out, True, False)
+        return make
+
+    def gray(dt):
+        def make(src):
+            out = torch.empty(src.shape[:2] + (1,), dtype=dt, device="cuda")
+            return lambda s: kr.rgb_to_gray(s, out)
+        return make
+
+    u8, f32 = torch.uint8, torch.float32
+    cases = [  # name, source size, output size, output bytes/px, source dtype, launcher
+        ("nearest_down_u8", big, small, 3, u8, nearest(small, u8)),
+        ("nearest_down_f32", big, small, 12, u8, nearest(small, f32)),
+        ("nearest_up_u8", small, big, 3, u8, nearest(big, u8)),
+        ("nearest_up_f32", small, big, 12, u8, nearest(big, f32)),
+        ("flip_u8", big, big, 3, u8, flip(u8)),
+        ("flip_f32", big, big, 12, f32, flip(f32)),
+        ("gray_u8", big, big, 1, u8, gray(u8)),
+        ("gray_f32", big, big, 4, u8, gray(f32)),
+    ]
+    for name, (h, w), (dh, dw), obytes, st, make in cases:
         img = wl.mixed_u8(h, w, 3, seed=0)
+        if st == torch.float32:
+            img = img.astype(np.float32)
         srcs = [torch.from_numpy(img).cuda() for _ in range(copies)]
-        out = torch.empty((dh, dw, 3), dtype=dt, device="cuda")
+        launch = make(srcs[0])
         for i in range(args.warmup):
-            kr.resize_nearest(srcs[i % copies], out)
+            launch(srcs[i % copies])
         reps = max(args.steps, 20)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
         for i in range(reps):
-            kr.resize_nearest(srcs[i % copies], out)
+            launch(srcs[i % copies])
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / reps
-        alg = nearest_touched_bytes(h, w, dh, dw) + dh * dw * 3 * (1 if dt == torch.uint8 else 4)
+        esize = 4 if st == torch.float32 else 1
+        src_bytes = (nearest_touched_bytes(h, w, dh, dw, esize=esize) if name.startswith("nearest")
+                     else h * w * 3 * esize)
+        alg = src_bytes + dh * dw * obytes
         gbps = alg / (ms * 1e-3) / 1e9
         kern[name] = {"avg_us": round(ms * 1e3, 3), "alg_bytes": alg, "GBps": round(gbps, 1),
                       "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(dh * dw / (ms * 1e-3) / 1e9, 2),
-                      "traffic": _traffic_from_profiles("nearest_" + name)}
+                      "traffic": _traffic_from_profiles(name)}
         total_px += dh * dw
         total_ms += ms
         del srcs
     dom = max(kern, key=lambda n: kern[n]["avg_us"])
     k = kern[dom]
     return {
-        "metric": "output Gpixels/s (nearest-neighbour resize 4K -> 1080p and 1080p -> 4K, u8 and f32 outputs)",
+        "metric": "output Gpixels/s (nearest resize 4K <-> 1080p, flip and RGB->gray at 4K, u8 and f32 outputs)",
         "value": round(total_px / (total_ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(total_ms, 4),
-        "config": {"workload": "nearest: 3840x2160x3 u8 -> 1920x1080 and 1920x1080x3 u8 -> 3840x2160, "
-                               "half-pixel centres, u8 and f32 outputs, cold sources", "px_per_step": total_px},
-        "roofline": {"bound": "hbm", "kernel": "nearest_" + dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS,
+        "config": {"workload": "ops: 3840x2160x3 u8 (f32 for the f32 flip) and 1920x1080x3 u8 sources, "
+                               "one launch of each operator per step, cold sources", "px_per_step": total_px},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": k["frac"], "traffic": k["traffic"], "alg_bytes_per_launch": k["alg_bytes"],
                      "avg_launch_us": k["avg_us"]},
         "kernels": kern,
@@ -508,7 +543,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve", "nearest"])
+    ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve", "ops"])
     ap.add_argument("--cold-copies", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "file", "live", "off"],
@@ -545,7 +580,7 @@ def main():
     copy_gbps = _hbm_copy_ceiling(torch, kr)
     if args.workload != "4k":
         fn = {"batch": bench_batch, "warpbatch": bench_warpbatch, "serve": bench_serve,
-              "nearest": bench_nearest}[args.workload]
+              "ops": bench_ops}[args.workload]
         r = fn(args, torch, kr, wl)
         out = {"metric": r.pop("metric"), "value": r.pop("value"), "unit": r.pop("unit")}
         out.update(common)

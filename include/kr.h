@@ -100,6 +100,25 @@ kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dty
                             const kr_normalize *norm, void *stream);
 
 /*
+ * Flip of one image (Sec. III "horizontal flip"): dst(x, y) = src(flip_x ?
+ * w-1-x : x, flip_y ? h-1-y : y), every channel; src and dst have the same
+ * size and type t (U8 or F32; f32 samples are moved bit for bit).
+ * flip_x, flip_y: 0 or 1.
+ */
+kr_status kr_flip(const void *src, int h, int w, int c, kr_dtype t, void *dst, int flip_x, int flip_y,
+                  void *stream);
+
+/*
+ * RGB to gray of one image (Sec. III "RGB to grayscale"), ITU-R BT.601 luma:
+ * src h x w x 3, dst h x w x 1.  U8 -> U8: (4899 R + 9617 G + 1868 B + 2^13)
+ * >> 14 (OpenCV-style 14-bit weights summing to 2^14).  F32 output: 0.299 R +
+ * 0.587 G + 0.114 B on the sample scale, then norm (mean[0], std[0]) if given.
+ * Type pairs as for the resizes.
+ */
+kr_status kr_rgb_to_gray(const void *src, int h, int w, kr_dtype src_t, void *dst, kr_dtype dst_t,
+                         const kr_normalize *norm, void *stream);
+
+/*
  * Bilinear affine warp of one image (Sec. II-A geometric transforms).
  * m: HOST pointer to the row-major 2x3 matrix [[a, b, c], [d, e, f]].  It
  * maps source to destination unless flags contains KR_WARP_INVERSE_MAP.  A

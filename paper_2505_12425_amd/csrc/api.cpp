@@ -202,6 +202,50 @@ kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dty
     return KR_OK;
 }
 
+kr_status kr_flip(const void *src, int h, int w, int c, kr_dtype t, void *dst, int flip_x, int flip_y, void *stream)
+{
+    clear_error();
+    kr_status s = check_common(src, h, w, c, t, dst, h, w, t, KR_BORDER_REPLICATE, 0.0f, nullptr);
+    if (s != KR_OK)
+        return s;
+    if ((flip_x != 0 && flip_x != 1) || (flip_y != 0 && flip_y != 1))
+        return fail(KR_ERR_INVALID_ARGUMENT, "flip flags must be 0 or 1");
+    const hipError_t err = launch_flip(c, t, src, dst, h, w, flip_x, flip_y, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "flip launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
+kr_status kr_rgb_to_gray(const void *src, int h, int w, kr_dtype src_t, void *dst, kr_dtype dst_t,
+                         const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    if (!((src_t == KR_U8 && dst_t == KR_U8) || (src_t == KR_U8 && dst_t == KR_F32) ||
+          (src_t == KR_F32 && dst_t == KR_F32)))
+        return fail(KR_ERR_UNSUPPORTED, "dtype pair (%d -> %d) not supported", (int)src_t, (int)dst_t);
+    kr_status s = check_image("src", src, h, w, 3);
+    if (s == KR_OK)
+        s = check_image("dst", dst, h, w, 1);
+    if (s != KR_OK)
+        return s;
+    if (norm) {
+        if (dst_t != KR_F32)
+            return fail(KR_ERR_INVALID_ARGUMENT, "normalisation needs an f32 destination");
+        if (!std::isfinite(norm->mean[0]) || !std::isfinite(norm->std[0]) || norm->std[0] == 0.0f)
+            return fail(KR_ERR_INVALID_ARGUMENT, "normalisation has a bad mean/std");
+    }
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+    const uintptr_t s1 = s0 + (uintptr_t)h * (uintptr_t)w * 3 * elem_size(src_t);
+    const uintptr_t d1 = d0 + (uintptr_t)h * (uintptr_t)w * elem_size(dst_t);
+    if (s0 < d1 && d0 < s1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src and dst overlap");
+    const Epilogue e = make_epilogue(1, KR_BORDER_REPLICATE, 0.0f, norm);
+    const hipError_t err = launch_gray(src_t, dst_t, src, dst, h, w, e, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "gray launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
 kr_status kr_invert_affine(const double m[6], double inv[6])
 {
     clear_error();

@@ -31,25 +31,6 @@ struct NearestJob {
     double rx, ry;  // 1 / (2 dw), 1 / (2 dh), rounded
 };
 
-// Source sample of C u8 channels at pixel index lin (byte c = channel c).
-template <int C>
-__device__ __forceinline__ uint32_t load_u8_px(const uint8_t *__restrict__ src, size_t nbytes, size_t lin)
-{
-    if constexpr (C == 4) {
-        return *reinterpret_cast<const uint32_t *>(src + lin * 4);
-    } else if constexpr (C == 3) {
-        const size_t b = lin * 3, f = b & ~(size_t)3;
-        if (f + 8 <= nbytes) {
-            struct __attribute__((packed, aligned(4))) D2 { uint32_t a, b; };
-            const D2 d = *reinterpret_cast<const D2 *>(src + f);
-            return __builtin_amdgcn_alignbyte(d.b, d.a, (uint32_t)(b & 3)) & 0xFFFFFFu;
-        }
-        return load_px_bytes<3>(src, lin);
-    } else {
-        return load_px_bytes<C>(src, lin);
-    }
-}
-
 template <int C, bool SRC_F32, bool DST_F32>
 __global__ __launch_bounds__(NN_TX * NN_TY) void k_nearest(NearestJob j, Epilogue e)
 {

@@ -97,6 +97,28 @@ __device__ __forceinline__ uint32_t load_px_bytes(const uint8_t *src, size_t lin
     return v;
 }
 
+// Source pixel of C u8 channels at pixel index lin (byte c = channel c), in
+// an image of nbytes bytes: RGBA one dword, RGB a dword-aligned 8-byte load
+// (bytewise at the very end of the buffer), fewer channels bytewise.
+template <int C>
+__device__ __forceinline__ uint32_t load_u8_px(const uint8_t *__restrict__ src, size_t nbytes, size_t lin)
+{
+    if constexpr (C == 4) {
+        return *reinterpret_cast<const uint32_t *>(src + lin * 4);
+    } else if constexpr (C == 3) {
+        const size_t b = lin * 3, f = b & ~(size_t)3;
+        if (f + 8 <= nbytes) {
+            struct __attribute__((packed, aligned(4))) D2 { uint32_t a, b; };
+            const D2 d = *reinterpret_cast<const D2 *>(src + f);
+            return __builtin_amdgcn_alignbyte(d.b, d.a, (uint32_t)(b & 3)) & 0xFFFFFFu;
+        }
+        return load_px_bytes<3>(src, lin);
+    } else {
+        return load_px_bytes<C>(src, lin);
+    }
+}
+
+
 // ------------------------------------------------------------------ pixel math
 // u8 interpolation of one pixel from its four tap dwords (byte c = channel c).
 // wxp packs the horizontal weights w0 | w1 << 16 (w0 + w1 = 2048); wy0_4,
@@ -219,8 +241,11 @@ __device__ __forceinline__ uint32_t pack_px(const uint32_t (&v)[C])
 template <int C, bool F32>
 __device__ __forceinline__ bool store4_aligned(int dw)
 {
+    // u8: 4 pixels are 4 (C = 1), 8, 12 (dword-aligned) or 16 bytes; f32: 16,
+    // 32, 48 or 64 bytes, stored as 16-byte vectors
     const size_t row_bytes = (size_t)dw * C * (F32 ? 4 : 1);
-    return (row_bytes & ((C == 3 && !F32) ? 3 : 15)) == 0;
+    const size_t mask = F32 ? 15 : (C == 1 || C == 3 ? 3 : (C == 2 ? 7 : 15));
+    return (row_bytes & mask) == 0;
 }
 
 // Four u8 pixels (pixel k = P[k], byte c = channel c); n valid pixels.
@@ -234,8 +259,15 @@ __device__ __forceinline__ void store_u8_4(uint8_t *p, int n, bool aligned, cons
             *reinterpret_cast<W3 *>(p) = W3{__builtin_amdgcn_perm(P[1], P[0], 0x04020100u),
                                             __builtin_amdgcn_perm(P[2], P[1], 0x05040201u),
                                             __builtin_amdgcn_perm(P[3], P[2], 0x06050402u)};
-        } else {
+        } else if constexpr (C == 4) {
             *reinterpret_cast<u32x4 *>(p) = u32x4{P[0], P[1], P[2], P[3]};
+        } else if constexpr (C == 2) {
+            *reinterpret_cast<u32x2 *>(p) = u32x2{__builtin_amdgcn_perm(P[1], P[0], 0x05040100u),
+                                                 __builtin_amdgcn_perm(P[3], P[2], 0x05040100u)};
+        } else {
+            *reinterpret_cast<uint32_t *>(p) =
+                __builtin_amdgcn_perm(__builtin_amdgcn_perm(P[3], P[2], 0x0C0C0400u),
+                                      __builtin_amdgcn_perm(P[1], P[0], 0x0C0C0400u), 0x05040100u);
         }
     } else {
         for (int k = 0; k < n; k++)
@@ -254,10 +286,15 @@ __device__ __forceinline__ void store_f32_4(float *p, int n, bool aligned, const
             q[0] = f32x4{o[0][0], o[0][1], o[0][2], o[1][0]};
             q[1] = f32x4{o[1][1], o[1][2], o[2][0], o[2][1]};
             q[2] = f32x4{o[2][2], o[3][0], o[3][1], o[3][2]};
-        } else {
+        } else if constexpr (C == 4) {
 #pragma unroll
             for (int k = 0; k < 4; k++)
                 q[k] = f32x4{o[k][0], o[k][1], o[k][2], o[k][3]};
+        } else if constexpr (C == 2) {
+            q[0] = f32x4{o[0][0], o[0][1], o[1][0], o[1][1]};
+            q[1] = f32x4{o[2][0], o[2][1], o[3][0], o[3][1]};
+        } else {
+            q[0] = f32x4{o[0][0], o[1][0], o[2][0], o[3][0]};
         }
     } else {
         for (int k = 0; k < n; k++)

@@ -69,6 +69,10 @@ def lib():
     L.kr_warp_affine.restype = i
     L.kr_resize_nearest.argtypes = [vp, i, i, i, i, vp, i, i, i, npp, vp]
     L.kr_resize_nearest.restype = i
+    L.kr_flip.argtypes = [vp, i, i, i, i, vp, i, i, vp]
+    L.kr_flip.restype = i
+    L.kr_rgb_to_gray.argtypes = [vp, i, i, i, vp, i, npp, vp]
+    L.kr_rgb_to_gray.restype = i
     L.kr_invert_affine.argtypes = [dp, dp]
     L.kr_invert_affine.restype = i
     L.kr_status_string.argtypes = [i]
@@ -181,6 +185,24 @@ def resize_nearest(src, dst, mean=None, std=None, stream=None) -> None:
     if dc != c:
         raise ValueError("src and dst channel counts differ")
     check(lib().kr_resize_nearest(sp, sh, sw, c, st, dp_, dh, dw, dt, _normalize(mean, std, c), _stream(stream)))
+
+
+def flip(src, dst, flip_x: bool = True, flip_y: bool = False, stream=None) -> None:
+    """kr_flip on torch tensors of the same shape and dtype."""
+    sp, h, w, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if (dh, dw, dc, dt) != (h, w, c, st):
+        raise ValueError("flip needs src and dst of the same shape and dtype")
+    check(lib().kr_flip(sp, h, w, c, st, dp_, int(flip_x), int(flip_y), _stream(stream)))
+
+
+def rgb_to_gray(src, dst, mean=None, std=None, stream=None) -> None:
+    """kr_rgb_to_gray: src HxWx3 -> dst HxW(x1)."""
+    sp, h, w, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if c != 3 or dc != 1 or (dh, dw) != (h, w):
+        raise ValueError("rgb_to_gray needs HxWx3 -> HxWx1")
+    check(lib().kr_rgb_to_gray(sp, h, w, st, dp_, dt, _normalize(mean, std, 1), _stream(stream)))
 
 
 def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, border_value: float = 0.0,

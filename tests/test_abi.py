@@ -272,3 +272,16 @@ def test_nearest_validation():
     assert f(A, 480, 640, 3, kr.U8, B, 240, 320, kr.U8, norm_ptr(), None) == kr.ERR_INVALID_ARGUMENT
     assert f(A, 480, 640, 3, kr.U8, A + 64, 240, 320, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT  # overlap
     assert f(A + 4, 480, 640, 3, kr.U8, B, 240, 320, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT  # misaligned
+
+
+def test_flip_and_gray_validation():
+    L = kr.lib()
+    assert L.kr_flip(A, 10, 10, 3, kr.U8, B, 2, 0, None) == kr.ERR_INVALID_ARGUMENT
+    assert L.kr_flip(A, 10, 10, 5, kr.U8, B, 1, 0, None) == kr.ERR_UNSUPPORTED
+    assert L.kr_flip(A, 10, 10, 3, kr.U8, A + 16, 1, 0, None) == kr.ERR_INVALID_ARGUMENT  # overlap
+    assert L.kr_flip(None, 10, 10, 3, kr.U8, B, 1, 0, None) == kr.ERR_INVALID_ARGUMENT
+    g = L.kr_rgb_to_gray
+    assert g(A, 10, 10, kr.F32, B, kr.U8, None, None) == kr.ERR_UNSUPPORTED
+    assert g(A, 10, 10, kr.U8, B, kr.U8, norm_ptr(), None) == kr.ERR_INVALID_ARGUMENT
+    assert g(A, 0, 10, kr.U8, B, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT
+    assert g(A, 10, 10, kr.U8, A + 288, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT  # dst inside src (300 B)

@@ -46,7 +46,7 @@ def test_4k_down_and_up():
     check(small, 2160, 3840, "1080p -> 4K")
 
 
-SHAPES = [(17, 23, 40, 61), (40, 61, 17, 23), (100, 100, 33, 77), (1, 1, 7, 9), (1, 50, 3, 17),
+SHAPES = [(50, 70, 48, 64), (64, 64, 128, 128), (17, 23, 40, 61), (40, 61, 17, 23), (100, 100, 33, 77), (1, 1, 7, 9), (1, 50, 3, 17),
           (31, 1, 5, 3), (333, 257, 333, 257), (64, 64, 1, 1), (9, 1000, 13, 255), (1, 32767, 2, 5)]
 
 
