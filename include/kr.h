@@ -273,9 +273,9 @@ void kr_server_destroy(kr_server *server);
  * scrub: NULL (launches timed back to back: a source that stays in the
  * caches) or a DEVICE buffer of scrub_bytes (16-byte aligned, >= 32, best
  * larger than the 256 MB last-level cache) overlapping no other argument,
- * whose contents the tuner overwrites before each timed launch so that the
- * source is read from HBM, as in a stream of distinct images; the median of
- * those reps is then used.
+ * whose contents the tuner overwrites before each launch so that the source
+ * is read from HBM and the previous output is written back, as in a stream
+ * of distinct images; the time of the overwrites alone is subtracted.
  * Only u8 sources with 3 or 4 channels have configurations
  * (KR_ERR_UNSUPPORTED otherwise).
  * kr_autotune_batch: same arguments as kr_resize_batch plus reps, scrub and

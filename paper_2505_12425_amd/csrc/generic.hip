@@ -61,14 +61,24 @@ hipError_t launch_generic(int op, int c, kr_dtype st, kr_dtype dt, const ImageJo
 
 // ---------------------------------------------------------------- copy probe
 // 16-byte vector copy: the bandwidth ceiling the resampling kernels are
-// compared with.  Grid-stride over 16-byte chunks, byte tail by one thread.
+// compared with.  Grid-stride over groups of four 16-byte chunks per thread
+// (four loads in flight before the stores), byte tail by one thread.
 __global__ __launch_bounds__(256) void k_copy(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src,
                                               size_t n16, uint8_t *dst_b, const uint8_t *src_b,
                                               size_t bytes)
 {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    const size_t stride = (size_t)gridDim.x * 1024;
+    for (size_t b = (size_t)blockIdx.x * 1024 + threadIdx.x; b < n16; b += stride) {
+        u32x4 r[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (b + k * 256 < n16)
+                r[k] = src[b + k * 256];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (b + k * 256 < n16)
+                dst[b + k * 256] = r[k];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (size_t b = n16 * 16; b < bytes; b++)
             dst_b[b] = src_b[b];
@@ -77,9 +87,9 @@ __global__ __launch_bounds__(256) void k_copy(u32x4 *__restrict__ dst, const u32
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 256 * 16)
-        blocks = 256 * 16;
+    size_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 256 * 8)
+        blocks = 256 * 8;
     if (blocks < 1)
         blocks = 1;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4 *)dst, (const u32x4 *)src,

@@ -36,10 +36,11 @@ std::vector<TileCfg> image_candidates(int op);
 std::vector<TileCfg> batch_candidates(int op);
 
 // Duration (ms) of one call of `launch` on stream s.  Without a scrub buffer:
-// reps calls back to back between one event pair, averaged.  With one: each
-// call timed alone right after the buffer's first half has been copied over
-// its second (which evicts the caller's source from the caches, as for a
-// source streamed from HBM), median of reps.  Synchronises s.
+// reps calls back to back between one event pair, averaged.  With one: reps
+// pairs (copy the buffer's first half over its second, which evicts the
+// caller's source from the caches; call) minus reps copies alone, averaged,
+// so that the call is charged for its HBM reads and its output's write-back.
+// Synchronises s.
 hipError_t time_launches(const std::function<hipError_t()> &launch, int reps, void *scrub, size_t scrub_bytes,
                          hipStream_t s, float &ms);
 
