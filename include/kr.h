@@ -168,6 +168,22 @@ kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src
                           void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Destination layouts of the batched forms: interleaved HWC (as everywhere
+ * else) or planar CHW (channel c of pixel (x, y) at c * dst_h * dst_w +
+ * y * dst_w + x; a batch of equal-size outputs packed back to back is then an
+ * NCHW tensor, the layout models consume).
+ */
+#define KR_LAYOUT_HWC 0
+#define KR_LAYOUT_CHW 1
+
+/* kr_resize_batch with an explicit destination layout (KR_LAYOUT_*);
+ * KR_ERR_INVALID_ARGUMENT for another value.  The destination of each item
+ * still spans dst_h * dst_w * c samples. */
+kr_status kr_resize_batch_ex(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                             kr_border border, float border_value, const kr_normalize *norm, int dst_layout,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * A reusable batch: kr_batch_plan_create validates the items, builds the
  * work-list once (it allocates and fills its own device memory, synchronously)
  * and captures the batch's launches into a HIP graph (kernel nodes only).
@@ -180,6 +196,10 @@ typedef struct kr_batch_plan kr_batch_plan;
 kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtype src_t,
                                kr_dtype dst_t, kr_border border, float border_value,
                                const kr_normalize *norm, kr_batch_plan **plan);
+/* kr_batch_plan_create with an explicit destination layout (KR_LAYOUT_*). */
+kr_status kr_batch_plan_create_ex(const kr_batch_item *items, int n, int c, kr_dtype src_t,
+                                  kr_dtype dst_t, kr_border border, float border_value,
+                                  const kr_normalize *norm, int dst_layout, kr_batch_plan **plan);
 kr_status kr_batch_plan_launch(kr_batch_plan *plan, void *stream);
 void kr_batch_plan_destroy(kr_batch_plan *plan);
 

@@ -287,7 +287,17 @@ kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src
                           float border_value, const kr_normalize *norm, void *workspace, size_t workspace_bytes,
                           void *stream)
 {
+    return kr_resize_batch_ex(items, n, c, src_t, dst_t, border, border_value, norm, KR_LAYOUT_HWC, workspace,
+                              workspace_bytes, stream);
+}
+
+kr_status kr_resize_batch_ex(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                             kr_border border, float border_value, const kr_normalize *norm, int dst_layout,
+                             void *workspace, size_t workspace_bytes, void *stream)
+{
     clear_error();
+    if (dst_layout != KR_LAYOUT_HWC && dst_layout != KR_LAYOUT_CHW)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown destination layout %d", dst_layout);
     std::vector<ImageJob> rs, ws;
     kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, rs, ws);
     if (st != KR_OK)
@@ -301,7 +311,8 @@ kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src
     if (workspace_bytes < kr_resize_batch_workspace_size(n))
         return fail(KR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", workspace_bytes,
                     kr_resize_batch_workspace_size(n));
-    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    Epilogue e = make_epilogue(c, border, border_value, norm);
+    e.planar = dst_layout == KR_LAYOUT_CHW;
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = dst_t == KR_F32;
     const std::vector<ImageJob> imgs[2] = {rs, ws};
@@ -351,6 +362,13 @@ extern "C" {
 kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
                                kr_border border, float border_value, const kr_normalize *norm, kr_batch_plan **plan)
 {
+    return kr_batch_plan_create_ex(items, n, c, src_t, dst_t, border, border_value, norm, KR_LAYOUT_HWC, plan);
+}
+
+kr_status kr_batch_plan_create_ex(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                                  kr_border border, float border_value, const kr_normalize *norm, int dst_layout,
+                                  kr_batch_plan **plan)
+{
     clear_error();
     if (!plan)
         return fail(KR_ERR_INVALID_ARGUMENT, "plan pointer is NULL");
@@ -363,7 +381,10 @@ kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtyp
         return fail(KR_ERR_INVALID_ARGUMENT, "a plan needs at least one item");
     if (!tiled_supported(c, src_t))
         return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
-    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    if (dst_layout != KR_LAYOUT_HWC && dst_layout != KR_LAYOUT_CHW)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown destination layout %d", dst_layout);
+    Epilogue e = make_epilogue(c, border, border_value, norm);
+    e.planar = dst_layout == KR_LAYOUT_CHW;
     const bool f32 = dst_t == KR_F32;
     kr_batch_plan *p = new (std::nothrow) kr_batch_plan();
     if (!p)

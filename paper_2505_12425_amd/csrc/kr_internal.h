@@ -19,6 +19,7 @@ struct Epilogue {
     float bval_f;    // CONSTANT border value as a sample (f32 path)
     int bval_i;      // CONSTANT border value as an integer sample (u8 path)
     int border;      // KR_BORDER_CONSTANT or KR_BORDER_REPLICATE
+    int planar;      // output layout: 0 = interleaved (HWC), 1 = planar (CHW, plane c at c * dh * dw)
 };
 
 // One image as the kernels see it.  For warps, inv is the inverse map with

@@ -372,6 +372,64 @@ __device__ __forceinline__ void store_run_f32(float *row, int x, int x_end, bool
     }
 }
 
+// Store one lane run of output row y, interleaved (HWC, through the runs
+// above) or planar (CHW: channel c of pixel (x, y) at c * dh * dw + y * dw +
+// x; a 4-pixel run is one dword (u8) or one 16-byte vector (f32) per plane
+// when the row width is a multiple of 4).  The branch is uniform per launch.
+template <int C, int PX>
+__device__ __forceinline__ void store_row_u8(const ImageJob &j, bool planar, int y, int x, int x_end, bool aligned,
+                                             const uint32_t (&P)[PX], uint32_t sel)
+{
+    if (!planar) {
+        store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + (size_t)y * (size_t)j.dw * C, x, x_end, aligned, P, sel);
+        return;
+    }
+    const size_t plane = (size_t)j.dh * (size_t)j.dw;
+    uint8_t *row = static_cast<uint8_t *>(j.dst) + (size_t)y * (size_t)j.dw + x;
+    const int n = min(PX, x_end - x);
+    if (n <= 0)
+        return;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        if constexpr (PX == 4) {
+            if (n == 4 && (j.dw & 3) == 0) {
+                const uint32_t lo = __builtin_amdgcn_perm(P[1], P[0], 0x0C0C0400u + 0x00000101u * c);
+                const uint32_t hi = __builtin_amdgcn_perm(P[3], P[2], 0x0C0C0400u + 0x00000101u * c);
+                *reinterpret_cast<uint32_t *>(row + c * plane) = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+                continue;
+            }
+        }
+        for (int k = 0; k < n; k++)
+            row[c * plane + k] = (uint8_t)(P[k] >> (8 * c));
+    }
+}
+
+template <int C, int PX>
+__device__ __forceinline__ void store_row_f32(const ImageJob &j, bool planar, int y, int x, int x_end, bool aligned,
+                                              const float (&o)[PX][C])
+{
+    if (!planar) {
+        store_run_f32<C, PX>(static_cast<float *>(j.dst) + (size_t)y * (size_t)j.dw * C, x, x_end, aligned, o);
+        return;
+    }
+    const size_t plane = (size_t)j.dh * (size_t)j.dw;
+    float *row = static_cast<float *>(j.dst) + (size_t)y * (size_t)j.dw + x;
+    const int n = min(PX, x_end - x);
+    if (n <= 0)
+        return;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        if constexpr (PX == 4) {
+            if (n == 4 && (j.dw & 3) == 0) {
+                *reinterpret_cast<f32x4 *>(row + c * plane) = f32x4{o[0][c], o[1][c], o[2][c], o[3][c]};
+                continue;
+            }
+        }
+        for (int k = 0; k < n; k++)
+            row[c * plane + k] = o[k][c];
+    }
+}
+
 // ------------------------------------------------------------------ tile plan
 // Launch-wide LDS geometry: every tile of a launch stages into rows x pitch dwords.
 struct TileGeom {
@@ -727,7 +785,6 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
             break;
         const double rowX = __builtin_fma(m[1], (double)y, m[2]);
         const double rowY = __builtin_fma(m[4], (double)y, m[5]);
-        const size_t row_off = (size_t)y * (size_t)j.dw * C;
 #pragma unroll
         for (int c = 0; c < CPT; c++) {
             const int xr = p.ox0 + c * L::SEG + L::col0();
@@ -759,7 +816,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                     }
                     P[k] = pack_px<C>(v);
                 }
-                store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + row_off, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
             } else {
                 float o[PX][C];
 #pragma unroll
@@ -785,7 +842,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                     interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
                                   e, o[k]);
                 }
-                store_run_f32<C, PX>(static_cast<float *>(j.dst) + row_off, xr, x_end, aligned, o);
+                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
             }
         }
     }
@@ -833,7 +890,6 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
         const int y0 = (int)tab[2 * TW + rr];
         const uint32_t rw = tab[2 * TW + TH + rr];
         const int s0 = (2 * rr) * pitch;
-        const size_t row_off = (size_t)y * (size_t)j.dw * C;
         const bool vy0 = (unsigned)y0 < (unsigned)H, vy1 = (unsigned)(y0 + 1) < (unsigned)H;
 #pragma unroll
         for (int c = 0; c < CPT; c++) {
@@ -858,7 +914,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                     }
                     P[k] = pack_px<C>(v);
                 }
-                store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + row_off, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
             } else {
                 const float fy = __builtin_bit_cast(float, rw);
                 float o[PX][C];
@@ -878,7 +934,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                     interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
                                   e, o[k]);
                 }
-                store_run_f32<C, PX>(static_cast<float *>(j.dst) + row_off, xr, x_end, aligned, o);
+                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
             }
         }
     }
@@ -1009,7 +1065,6 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
         const int y = p.oy0 + rr;
         if (y > p.oy1)
             break;
-        const size_t row_off = (size_t)y * (size_t)j.dw * C;
         double rowX = 0, rowY = 0;
         int ry0 = 0;
         uint32_t rw = 0;
@@ -1062,9 +1117,9 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
                     gather_px_f32<C>(j, e, x0, y0, fx, fy, o[k]);
             }
             if constexpr (!F32)
-                store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + row_off, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
             else
-                store_run_f32<C, PX>(static_cast<float *>(j.dst) + row_off, xr, x_end, aligned, o);
+                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
         }
     }
 }

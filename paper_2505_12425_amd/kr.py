@@ -31,6 +31,8 @@ REPLICATE = 1
 WARP_INVERSE_MAP = 1
 OP_RESIZE = 0
 OP_WARP = 1
+LAYOUT_HWC = 0
+LAYOUT_CHW = 1
 
 
 class KrError(RuntimeError):
@@ -89,6 +91,10 @@ def lib():
         L.kr_resize_batch.restype = i
         L.kr_batch_plan_create.argtypes = [bip, i, i, i, i, i, f, npp, ctypes.POINTER(vp)]
         L.kr_batch_plan_create.restype = i
+        L.kr_resize_batch_ex.argtypes = [bip, i, i, i, i, i, f, npp, i, vp, ctypes.c_size_t, vp]
+        L.kr_resize_batch_ex.restype = i
+        L.kr_batch_plan_create_ex.argtypes = [bip, i, i, i, i, i, f, npp, i, ctypes.POINTER(vp)]
+        L.kr_batch_plan_create_ex.restype = i
         L.kr_batch_plan_launch.argtypes = [vp, vp]
         L.kr_batch_plan_launch.restype = i
         L.kr_batch_plan_destroy.argtypes = [vp]
@@ -232,16 +238,25 @@ def hbm_copy(dst, src, nbytes: int | None = None, stream=None) -> None:
 
 
 # ---------------------------------------------------------------- batches
-def _batch_items(specs):
+def _image_chw(t):
+    """(pointer, H, W, C, kr_dtype) of a contiguous CHW device tensor."""
+    if t.dim() != 3:
+        raise ValueError("planar tensor must be CxHxW")
+    ptr, c, h, w, dt = _image(t)  # dims read as (C, H, W)
+    return ptr, h, w, c, dt
+
+
+def _batch_items(specs, layout: int = LAYOUT_HWC):
     """ctypes array of BatchItem from specs: dicts with keys op ("resize" or
-    "warp"), src, dst (tensors), and for warps m (2x3) and optional inverse."""
+    "warp"), src, dst (tensors; dst CxHxW for the planar layout), and for
+    warps m (2x3) and optional inverse."""
     n = len(specs)
     arr = (BatchItem * max(n, 1))()
     c = st = dt = None
     for i, sp in enumerate(specs):
         sp_ = dict(sp)
         sptr, sh, sw, sc, s_t = _image(sp_["src"])
-        dptr, dh, dw, dc, d_t = _image(sp_["dst"])
+        dptr, dh, dw, dc, d_t = _image_chw(sp_["dst"]) if layout == LAYOUT_CHW else _image(sp_["dst"])
         if sc != dc or (c is not None and (sc != c or s_t != st or d_t != dt)):
             raise ValueError("batch items must share channel count and dtypes")
         c, st, dt = sc, s_t, d_t
@@ -266,19 +281,20 @@ def batch_workspace_size(n: int) -> int:
 
 
 def resize_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None, workspace=None,
-                 stream=None) -> None:
+                 stream=None, layout: int = LAYOUT_HWC) -> None:
     """kr_resize_batch: every item of `specs` in one launch per operation.
     `workspace` is a device tensor of at least batch_workspace_size(n) bytes
     (allocated here if None)."""
     import torch
-    arr, n, c, st, dt = _batch_items(specs)
+    arr, n, c, st, dt = _batch_items(specs, layout)
     if n == 0:
         return
     need = batch_workspace_size(n)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
-    check(lib().kr_resize_batch(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
-                                workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream)))
+    check(lib().kr_resize_batch_ex(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
+                                   int(layout), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                   _stream(stream)))
 
 
 # ---------------------------------------------------------------- autotuning
@@ -344,12 +360,13 @@ class BatchPlan:
     """kr_batch_plan_*: a validated work-list captured in a HIP graph; launch()
     replays it.  The tensors named by the specs must outlive the plan."""
 
-    def __init__(self, specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None):
-        arr, n, c, st, dt = _batch_items(specs)
+    def __init__(self, specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
+                 layout: int = LAYOUT_HWC):
+        arr, n, c, st, dt = _batch_items(specs, layout)
         self._keep = [sp["src"] for sp in specs] + [sp["dst"] for sp in specs]
         h = ctypes.c_void_p()
-        check(lib().kr_batch_plan_create(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
-                                         ctypes.byref(h)))
+        check(lib().kr_batch_plan_create_ex(arr, n, c, st, dt, border, float(border_value),
+                                            _normalize(mean, std, c), int(layout), ctypes.byref(h)))
         self._h = h
 
     def launch(self, stream=None) -> None:

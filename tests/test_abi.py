@@ -285,3 +285,14 @@ def test_flip_and_gray_validation():
     assert g(A, 10, 10, kr.U8, B, kr.U8, norm_ptr(), None) == kr.ERR_INVALID_ARGUMENT
     assert g(A, 0, 10, kr.U8, B, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT
     assert g(A, 10, 10, kr.U8, A + 288, kr.U8, None, None) == kr.ERR_INVALID_ARGUMENT  # dst inside src (300 B)
+
+
+def test_batch_layout_validation():
+    L = kr.lib()
+    ws = A + 0x10000000
+    assert L.kr_resize_batch_ex(batch_items(), 2, 3, 0, 0, 1, 0.0, None, 2, ws, 1 << 20, None) \
+        == kr.ERR_INVALID_ARGUMENT
+    h = ctypes.c_void_p()
+    assert L.kr_batch_plan_create_ex(batch_items(), 2, 3, 0, 0, 1, 0.0, None, -1, ctypes.byref(h)) \
+        == kr.ERR_INVALID_ARGUMENT
+    assert h.value is None

@@ -162,3 +162,48 @@ def test_warp_batch_all_lds_classes(out):
         else:
             assert_f32_close(got, oracle.warp(im, m, dh, dw, "f64", border=oracle.CONSTANT, bval=9, threads=TH),
                              f"item {i}")
+
+
+@pytest.mark.parametrize("c,out", [(3, "f32"), (3, "u8"), (4, "u8"), (4, "f32")])
+def test_planar_layout_equals_interleaved(c, out):
+    """CHW destinations hold exactly the HWC results, transposed, for a mixed
+    batch of resizes and warps (single launch and plan); spot-checked against
+    the oracle."""
+    rng = np.random.default_rng(40 + c)
+    dt = torch.uint8 if out == "u8" else torch.float32
+    mean = (MEAN + (0.5,))[:c] if out == "f32" else None
+    std = (STD + (0.25,))[:c] if out == "f32" else None
+    hwc, chw, refs = [], [], []
+    for i in range(12):
+        h, w = int(rng.integers(50, 700)), int(rng.integers(50, 700))
+        im = wl.uniform_u8(h, w, c, seed=700 + i)
+        s = torch.from_numpy(im).cuda()
+        th, tw = int(rng.choice([37, 224, 301])), int(rng.choice([64, 224, 255]))
+        sp = {"op": "resize", "src": s}
+        if i % 3 == 1:
+            sp = {"op": "warp", "src": s, "m": wl.affine_compose(h, w, rng.uniform(-30, 30), min(th, tw) / max(h, w),
+                                                                 0.05, (tw - w) / 2.0, (th - h) / 2.0)}
+        hwc.append(dict(sp, dst=torch.empty((th, tw, c), dtype=dt, device="cuda")))
+        chw.append(dict(sp, dst=torch.empty((c, th, tw), dtype=dt, device="cuda")))
+        refs.append((im, sp.get("m"), th, tw))
+    say(f"planar batch c={c} out={out}")
+    kr.resize_batch(hwc, border=kr.REPLICATE, mean=mean, std=std)
+    kr.resize_batch(chw, border=kr.REPLICATE, mean=mean, std=std, layout=kr.LAYOUT_CHW)
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(hwc, chw)):
+        assert np.array_equal(a["dst"].cpu().numpy().transpose(2, 0, 1), b["dst"].cpu().numpy()), f"item {k}"
+    plan = kr.BatchPlan(chw, border=kr.REPLICATE, mean=mean, std=std, layout=kr.LAYOUT_CHW)
+    for sp in chw:
+        sp["dst"].zero_()
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(hwc, chw)):
+        assert np.array_equal(a["dst"].cpu().numpy().transpose(2, 0, 1), b["dst"].cpu().numpy()), f"plan item {k}"
+    plan.close()
+    im, m, th, tw = refs[0]
+    got = chw[0]["dst"].cpu().numpy().transpose(1, 2, 0)
+    if out == "u8":
+        assert_u8_equal(got, oracle.resize(im, th, tw, "u8", oracle.REPLICATE, threads=TH), "item 0 vs oracle")
+    else:
+        assert_f32_close(got, oracle.resize(im, th, tw, "f64", oracle.REPLICATE, 0, mean, std, threads=TH),
+                         "item 0 vs oracle", std=std)
