@@ -60,6 +60,10 @@ def _load():
     lib.kro_flip.restype = i
     lib.kro_rgb_to_gray.argtypes = [vp, i, i, i, vp, i, dp, dp, i]
     lib.kro_rgb_to_gray.restype = i
+    lib.kro_invert_homography.argtypes = [dp, dp]
+    lib.kro_invert_homography.restype = i
+    lib.kro_warp_perspective.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, d, dp, dp, i]
+    lib.kro_warp_perspective.restype = i
     lib.kro_invert_affine.argtypes = [dp, dp]
     lib.kro_invert_affine.restype = i
     _lib = lib
@@ -187,3 +191,35 @@ def invert_affine(m6) -> np.ndarray:
     if lib.kro_invert_affine(mm, out) != 0:
         raise ValueError("singular affine matrix")
     return np.array(list(out), np.float64)
+
+
+def invert_homography(m9):
+    """The oracle's inverse of a 3x3 homography (adjugate formula)."""
+    lib = _load()
+    a = (ctypes.c_double * 9)(*[float(v) for v in np.asarray(m9, np.float64).reshape(9)])
+    out = (ctypes.c_double * 9)()
+    if lib.kro_invert_homography(a, out) != 0:
+        raise ValueError("singular homography")
+    return np.array(list(out))
+
+
+def warp_perspective(src: np.ndarray, m9, dh: int, dw: int, out: str = "u8", inverse: bool = False,
+                     border: int = CONSTANT, bval: float = 0.0, mean=None, std=None, threads: int = 1) -> np.ndarray:
+    """Oracle bilinear perspective warp.  ``m9`` is the row-major 3x3 homography,
+    source->destination unless ``inverse``."""
+    lib = _load()
+    src, st = _src_args(src)
+    h, w, c = src.shape
+    if out == "u8":
+        dst = np.zeros((dh, dw, c), np.uint8)
+        ot = 0
+    else:
+        dst = np.zeros((dh, dw, c), np.float64)
+        ot = 1
+    mm = (ctypes.c_double * 9)(*[float(v) for v in np.asarray(m9, np.float64).reshape(9)])
+    m, s, _keep = _norm_args(mean, std, c)
+    rc = lib.kro_warp_perspective(src.ctypes.data, h, w, c, st, dst.ctypes.data, dh, dw, ot, mm, int(inverse),
+                                  border, float(bval), m, s, threads)
+    if rc != 0:
+        raise ValueError("kro_warp_perspective rejected its arguments")
+    return dst

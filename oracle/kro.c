@@ -36,7 +36,9 @@
  * Nearest-neighbour resize (kro_resize_nearest) takes the sample at
  * floor((d + 1/2) * n_in / n_out) per axis, an exact integer quotient.
  * Flip (kro_flip) mirrors the pixel order; RGB to gray (kro_rgb_to_gray)
- * uses BT.601 luma weights (14-bit fixed point for u8 output).
+ * uses BT.601 luma weights (14-bit fixed point for u8 output).  The
+ * perspective warp (kro_warp_perspective) divides the homography's first two
+ * rows by its third, in binary64, then proceeds as the affine warp.
  *
  * Parity status: every function here is pinned by the tests in
  * tests/test_oracle.py (closed forms, exact permutations, an exact-rational
@@ -313,6 +315,80 @@ int kro_warp(const void *src, int sh, int sw, int c, int src_t,
         for (int x = 0; x < dw; x++) {
             double xs = fma(im[0], (double)x, fma(im[1], (double)y, im[2]));
             double ys = fma(im[3], (double)x, fma(im[4], (double)y, im[5]));
+            if (xs < -2.0) xs = -2.0;
+            if (xs > (double)sw + 1.0) xs = (double)sw + 1.0;
+            if (ys < -2.0) ys = -2.0;
+            if (ys > (double)sh + 1.0) ys = (double)sh + 1.0;
+            double fx0 = floor(xs), fy0 = floor(ys);
+            double fx = xs - fx0, fy = ys - fy0;
+            int64_t wx1 = (int64_t)nearbyint(2048.0 * fx);
+            int64_t wy1 = (int64_t)nearbyint(2048.0 * fy);
+            write_pixel(src, src_t, sh, sw, c, dst, out_t,
+                        ((size_t)y * (size_t)dw + (size_t)x) * (size_t)c,
+                        (int64_t)fx0, (int64_t)fy0, wx1, wy1, fx, fy,
+                        border, bval, mean, stdv);
+        }
+    }
+    return 0;
+}
+
+/* Inverse of a 3x3 homography m (row-major) by the adjugate: cofactors as
+ * differences of two rounded products, det = (m00 c00 + m01 c01) + m02 c02,
+ * inverse = cofactor matrix transposed, each entry divided by det.  Returns
+ * -1 if det is zero or not finite. */
+int kro_invert_homography(const double m[9], double inv[9])
+{
+    double c00 = m[4] * m[8] - m[5] * m[7];
+    double c01 = m[5] * m[6] - m[3] * m[8];
+    double c02 = m[3] * m[7] - m[4] * m[6];
+    double det = (m[0] * c00 + m[1] * c01) + m[2] * c02;
+    if (det == 0.0 || !isfinite(det))
+        return -1;
+    double c10 = m[2] * m[7] - m[1] * m[8];
+    double c11 = m[0] * m[8] - m[2] * m[6];
+    double c12 = m[1] * m[6] - m[0] * m[7];
+    double c20 = m[1] * m[5] - m[2] * m[4];
+    double c21 = m[2] * m[3] - m[0] * m[5];
+    double c22 = m[0] * m[4] - m[1] * m[3];
+    inv[0] = c00 / det; inv[1] = c10 / det; inv[2] = c20 / det;
+    inv[3] = c01 / det; inv[4] = c11 / det; inv[5] = c21 / det;
+    inv[6] = c02 / det; inv[7] = c12 / det; inv[8] = c22 / det;
+    return 0;
+}
+
+/* Bilinear perspective warp (a homography; the "geometric transforms" of
+ * Sec. II-A beyond the affine case).  m maps source to destination unless
+ * inverse.  Destination pixel (x, y): w = fma(h20, x, fma(h21, y, h22)),
+ * xs = fma(h00, x, fma(h01, y, h02)) / w, ys likewise (binary64, correctly
+ * rounded); a coordinate that is not a number (w = 0 over 0) reads as -2;
+ * then the clamp, taps, weights and borders of kro_warp. */
+int kro_warp_perspective(const void *src, int sh, int sw, int c, int src_t,
+                         void *dst, int dh, int dw, int out_t,
+                         const double m[9], int inverse,
+                         int border, double bval, const double *mean, const double *stdv,
+                         int nthreads)
+{
+    if (sh < 1 || sw < 1 || dh < 1 || dw < 1 || c < 1 || c > 4)
+        return -1;
+    double im[9];
+    if (inverse) {
+        for (int i = 0; i < 9; i++)
+            im[i] = m[i];
+    } else if (kro_invert_homography(m, im) != 0) {
+        return -1;
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int y = 0; y < dh; y++) {
+        for (int x = 0; x < dw; x++) {
+            double w = fma(im[6], (double)x, fma(im[7], (double)y, im[8]));
+            double xs = fma(im[0], (double)x, fma(im[1], (double)y, im[2])) / w;
+            double ys = fma(im[3], (double)x, fma(im[4], (double)y, im[5])) / w;
+            if (xs != xs)
+                xs = -2.0;
+            if (ys != ys)
+                ys = -2.0;
             if (xs < -2.0) xs = -2.0;
             if (xs > (double)sw + 1.0) xs = (double)sw + 1.0;
             if (ys < -2.0) ys = -2.0;

@@ -116,3 +116,49 @@ def resize_nearest(src: np.ndarray, dh: int, dw: int, out="u8", mean=None, std=N
                     v = float(v)
                     res[dy, dx, ch] = (v / 255.0 - mean[ch]) / std[ch] if mean is not None else v
     return res
+
+
+def invert_homography(m):
+    """Adjugate inverse of a 3x3 homography in binary64, each cofactor a
+    difference of two rounded products, det = (m00 c00 + m01 c01) + m02 c02,
+    each inverse entry the cofactor divided by det."""
+    a = [float(v) for v in np.asarray(m, np.float64).reshape(9)]
+    c00 = a[4] * a[8] - a[5] * a[7]
+    c01 = a[5] * a[6] - a[3] * a[8]
+    c02 = a[3] * a[7] - a[4] * a[6]
+    det = (a[0] * c00 + a[1] * c01) + a[2] * c02
+    c10 = a[2] * a[7] - a[1] * a[8]
+    c11 = a[0] * a[8] - a[2] * a[6]
+    c12 = a[1] * a[6] - a[0] * a[7]
+    c20 = a[1] * a[5] - a[2] * a[4]
+    c21 = a[2] * a[3] - a[0] * a[5]
+    c22 = a[0] * a[4] - a[1] * a[3]
+    return [c00 / det, c10 / det, c20 / det, c01 / det, c11 / det, c21 / det, c02 / det, c12 / det, c22 / det]
+
+
+def warp_perspective(src: np.ndarray, m, dh: int, dw: int, out="u8", inverse=False, border=0, bval=0,
+                     mean=None, std=None):
+    """Homography warp: w = fma(G, x, fma(H, y, I)); xs = fma(A, x, fma(B, y, C)) / w,
+    ys likewise, each quotient the binary64 rounding of the exact ratio; a
+    not-a-number coordinate reads as -2; then the affine warp's clamp and taps."""
+    h, w, c = src.shape
+    inv = [float(v) for v in np.asarray(m, np.float64).reshape(9)] if inverse else invert_homography(m)
+    dst = np.zeros((dh, dw, c), np.uint8 if out == "u8" else np.float64)
+    for y in range(dh):
+        for x in range(dw):
+            den = fma(inv[6], float(x), fma(inv[7], float(y), inv[8]))
+            num = [fma(inv[0], float(x), fma(inv[1], float(y), inv[2])),
+                   fma(inv[3], float(x), fma(inv[4], float(y), inv[5]))]
+            q = []
+            for v in num:
+                if den == 0.0:
+                    r = math.copysign(math.inf, v) * math.copysign(1.0, den) if v != 0.0 else -2.0
+                else:
+                    r = float(Fraction(v) / Fraction(den))
+                q.append(r)
+            xs = min(max(q[0], -2.0), w + 1.0)
+            ys = min(max(q[1], -2.0), h + 1.0)
+            fxs, fys = Fraction(xs), Fraction(ys)
+            x0, y0 = math.floor(fxs), math.floor(fys)
+            dst[y, x, :] = _blend(src, x0, y0, fxs - x0, fys - y0, out, border, bval, mean, std)
+    return dst

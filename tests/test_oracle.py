@@ -446,3 +446,46 @@ def test_gray_matches_integer_and_float_definitions():
     src = wl.uniform_f32(5, 8, 3, seed=1)
     g = oracle.rgb_to_gray(src, "f64")[..., 0]
     assert np.allclose(g, src.astype(np.float64) @ np.array([0.299, 0.587, 0.114]), rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------- perspective warp
+def test_homography_inverse():
+    assert np.array_equal(oracle.invert_homography([2, 0, 0, 0, 4, 0, 0, 0, 1]), [0.5, 0, 0, 0, 0.25, 0, 0, 0, 1])
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        m = np.eye(3) + rng.uniform(-0.3, 0.3, (3, 3))
+        inv = oracle.invert_homography(m).reshape(3, 3)
+        assert np.allclose(m @ inv, np.eye(3), atol=1e-12)
+        assert list(inv.reshape(9)) == bf.invert_homography(m)
+    with pytest.raises(ValueError):
+        oracle.invert_homography([1, 2, 3, 2, 4, 6, 0, 0, 1])
+
+
+def test_perspective_identity_and_affine_special_cases():
+    img = wl.uniform_u8(21, 27, 3, seed=8)
+    assert np.array_equal(oracle.warp_perspective(img, np.eye(3), 21, 27, "u8"), img)
+    inv6 = [0.93, 0.2, 1.7, -0.15, 1.04, -2.3]
+    inv9 = inv6 + [0.0, 0.0, 1.0]
+    for out in ("u8", "f64"):
+        a = oracle.warp(img, inv6, 19, 25, out, inverse=True, border=CONST, bval=11)
+        p = oracle.warp_perspective(img, inv9, 19, 25, out, inverse=True, border=CONST, bval=11)
+        assert np.array_equal(a, p), out
+    # a uniform third row divides exactly: [[1,0,0],[0,1,0],[0,0,2]] == affine scale 1/2
+    half = oracle.warp(img, [0.5, 0, 0, 0, 0.5, 0], 30, 40, "u8", inverse=True, border=REPL)
+    assert np.array_equal(oracle.warp_perspective(img, [1, 0, 0, 0, 1, 0, 0, 0, 2], 30, 40, "u8", inverse=True,
+                                                  border=REPL), half)
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_perspective_matches_bruteforce(k):
+    img = wl.uniform_u8(10 + k, 12, 3, seed=20 + k)
+    mats = [[1.05, 0.1, -0.5, -0.08, 0.97, 0.4, 0.01, -0.02, 1.0],
+            [0.9, -0.2, 2.0, 0.15, 1.1, -1.0, -0.03, 0.015, 1.02],
+            [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.12, 0.09, -0.6]]  # crosses the horizon
+    m = mats[k]
+    for border in (CONST, REPL):
+        exp = bf.warp_perspective(img, m, 9, 13, "u8", border=border, bval=40)
+        assert np.array_equal(oracle.warp_perspective(img, m, 9, 13, "u8", border=border, bval=40), exp)
+        expf = bf.warp_perspective(img, m, 9, 13, "f64", border=border, bval=40)
+        assert np.allclose(oracle.warp_perspective(img, m, 9, 13, "f64", border=border, bval=40), expf,
+                           rtol=0, atol=1e-9)

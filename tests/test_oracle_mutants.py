@@ -46,6 +46,12 @@ MUTANTS = [
      "1868 * (int64_t)p[0] + 9617 * (int64_t)p[1] + 4899 * (int64_t)p[2]"),
     ("gray truncation", "((acc + (1 << 13)) >> 14)", "(acc >> 14)"),
     ("flip shifted by one", "int sx = flip_x ? w - 1 - x : x;", "int sx = flip_x ? (w - x) % w : x;"),
+    ("perspective w row swapped", "double w = fma(im[6], (double)x, fma(im[7], (double)y, im[8]));",
+     "double w = fma(im[7], (double)x, fma(im[6], (double)y, im[8]));"),
+    ("homography cofactor sign", "double c01 = m[5] * m[6] - m[3] * m[8];",
+     "double c01 = m[3] * m[8] - m[5] * m[6];"),
+    ("perspective without division", "double xs = fma(im[0], (double)x, fma(im[1], (double)y, im[2])) / w;",
+     "double xs = fma(im[0], (double)x, fma(im[1], (double)y, im[2]));"),
     ("wrong tap row (f64)", "+ fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0 + 1, ch, border, bval);",
      "+ fy * fx * tap(src, src_t, sh, sw, c, x0 + 1, y0, ch, border, bval);"),
 ]
