@@ -133,6 +133,35 @@ kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype 
                          kr_border border, float border_value, const kr_normalize *norm,
                          void *stream);
 
+/*
+ * Bilinear perspective warp of one image (a homography; Sec. II-A geometric
+ * transforms beyond the affine case).  m: HOST pointer to the row-major 3x3
+ * matrix, source to destination unless flags contains KR_WARP_INVERSE_MAP
+ * (then it is the inverse map [[A, B, C], [D, E, F], [G, H, I]]; a forward
+ * matrix is inverted by kr_invert_homography).  Destination pixel (x, y):
+ * w = fma(G, x, fma(H, y, I)), xs = fma(A, x, fma(B, y, C)) / w,
+ * ys = fma(D, x, fma(E, y, F)) / w in binary64 (correctly rounded
+ * quotients); a quotient that is not a number reads as -2; then the clamp,
+ * taps, weights, borders and outputs of kr_warp_affine.  Returns
+ * KR_ERR_SINGULAR_MATRIX for a non-finite matrix or, for a forward matrix,
+ * det = 0 or |det| <= 1e-12 * max|m_ij|^3.
+ */
+kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_dtype src_t,
+                              void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                              const double m[9], int flags,
+                              kr_border border, float border_value, const kr_normalize *norm,
+                              void *stream);
+
+/*
+ * Inverse of the 3x3 homography m (host arrays, row-major) by the adjugate:
+ * cofactors c_ij as differences of two rounded products (c00 = m4 m8 - m5 m7,
+ * c01 = m5 m6 - m3 m8, c02 = m3 m7 - m4 m6, c10 = m2 m7 - m1 m8,
+ * c11 = m0 m8 - m2 m6, c12 = m1 m6 - m0 m7, c20 = m1 m5 - m2 m4,
+ * c21 = m2 m3 - m0 m5, c22 = m0 m4 - m1 m3), det = (m0 c00 + m1 c01) + m2 c02,
+ * inv[3 r + k] = c_kr / det.  Same singularity rule as kr_warp_perspective.
+ */
+kr_status kr_invert_homography(const double m[9], double inv[9]);
+
 /* One image of a batch.  op: 0 = resize, 1 = warp.  m and flags are read for
  * warps only (same meaning as in kr_warp_affine). */
 typedef struct {

@@ -246,6 +246,82 @@ kr_status kr_rgb_to_gray(const void *src, int h, int w, kr_dtype src_t, void *ds
     return KR_OK;
 }
 
+// Inverse of a 3x3 homography by the adjugate (fixed evaluation order:
+// cofactors as differences of two rounded products, det = (m00 c00 +
+// m01 c01) + m02 c02, entries divided by det).  Singular: det zero, not
+// finite, or |det| <= 1e-12 max|m_ij|^3.
+static kr_status invert_homography_impl(const double m[9], double inv[9])
+{
+    const double c00 = m[4] * m[8] - m[5] * m[7];
+    const double c01 = m[5] * m[6] - m[3] * m[8];
+    const double c02 = m[3] * m[7] - m[4] * m[6];
+    const double det = (m[0] * c00 + m[1] * c01) + m[2] * c02;
+    double mx = 0.0;
+    for (int i = 0; i < 9; i++)
+        mx = std::fmax(mx, std::fabs(m[i]));
+    if (det == 0.0 || !std::isfinite(det) || std::fabs(det) <= 1e-12 * mx * mx * mx)
+        return fail(KR_ERR_SINGULAR_MATRIX, "homography is singular (det %g)", det);
+    const double c10 = m[2] * m[7] - m[1] * m[8];
+    const double c11 = m[0] * m[8] - m[2] * m[6];
+    const double c12 = m[1] * m[6] - m[0] * m[7];
+    const double c20 = m[1] * m[5] - m[2] * m[4];
+    const double c21 = m[2] * m[3] - m[0] * m[5];
+    const double c22 = m[0] * m[4] - m[1] * m[3];
+    inv[0] = c00 / det; inv[1] = c10 / det; inv[2] = c20 / det;
+    inv[3] = c01 / det; inv[4] = c11 / det; inv[5] = c21 / det;
+    inv[6] = c02 / det; inv[7] = c12 / det; inv[8] = c22 / det;
+    return KR_OK;
+}
+
+kr_status kr_invert_homography(const double m[9], double inv[9])
+{
+    clear_error();
+    if (!m || !inv)
+        return fail(KR_ERR_INVALID_ARGUMENT, "NULL matrix pointer");
+    for (int i = 0; i < 9; i++)
+        if (!std::isfinite(m[i]))
+            return fail(KR_ERR_SINGULAR_MATRIX, "matrix entry %d is not finite", i);
+    return invert_homography_impl(m, inv);
+}
+
+kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst, int dst_h,
+                              int dst_w, kr_dtype dst_t, const double m[9], int flags, kr_border border,
+                              float border_value, const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    if (s != KR_OK)
+        return s;
+    if (flags & ~KR_WARP_INVERSE_MAP)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown warp flags 0x%x", flags);
+    if (!m)
+        return fail(KR_ERR_INVALID_ARGUMENT, "matrix pointer is NULL");
+    double inv[9];
+    for (int i = 0; i < 9; i++)
+        if (!std::isfinite(m[i]))
+            return fail(KR_ERR_SINGULAR_MATRIX, "matrix entry %d is not finite", i);
+    if (flags & KR_WARP_INVERSE_MAP) {
+        for (int i = 0; i < 9; i++)
+            inv[i] = m[i];
+    } else {
+        s = invert_homography_impl(m, inv);
+        if (s != KR_OK)
+            return s;
+    }
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    for (int i = 0; i < 6; i++)
+        j.inv[i] = inv[i];
+    for (int i = 0; i < 3; i++)
+        j.proj[i] = inv[6 + i];
+    const Epilogue e = make_epilogue(c, border, border_value, norm);
+    const hipError_t err = launch_persp(c, src_t, dst_t, j, e, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "perspective warp launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
 kr_status kr_invert_affine(const double m[6], double inv[6])
 {
     clear_error();

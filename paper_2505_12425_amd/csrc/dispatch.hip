@@ -21,4 +21,11 @@ hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const
     return launch_generic(OP_WARP, c, st, dt, j, e, s);
 }
 
+hipError_t launch_persp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
+{
+    if (tiled_supported(c, st))
+        return launch_tiled(OP_PERSP, c, dt, j, e, s);
+    return launch_generic(OP_PERSP, c, st, dt, j, e, s);
+}
+
 }  // namespace kr

@@ -10,6 +10,8 @@
 //    held as an exact rational; floor and remainder are integers;
 //  * warp: xs = fma(A, x, fma(B, y, C)), ys = fma(D, x, fma(E, y, F)) in
 //    binary64, clamped to [-2, W + 1] x [-2, H + 1];
+//  * perspective warp: the same two rows divided by w = fma(G, x, fma(H, y, I))
+//    (binary64 quotients; not-a-number reads as -2), then clamped;
 //  * u8 weights w1 = round-half-even(2048 frac), w0 = 2048 - w1; exact integer
 //    accumulation; out = (acc + 2^21) >> 22.  f32: unquantised weights.
 #include "kr_device.h"
@@ -32,6 +34,8 @@ static hipError_t launch_generic_t(int op, const ImageJob &j, const Epilogue &e,
     dim3 grid((j.dw + 63) / 64, (j.dh + 3) / 4);
     if (op == OP_RESIZE)
         hipLaunchKernelGGL((k_generic<C, S, D, OP_RESIZE>), grid, dim3(256), 0, s, j, e);
+    else if (op == OP_PERSP)
+        hipLaunchKernelGGL((k_generic<C, S, D, OP_PERSP>), grid, dim3(256), 0, s, j, e);
     else
         hipLaunchKernelGGL((k_generic<C, S, D, OP_WARP>), grid, dim3(256), 0, s, j, e);
     return hipGetLastError();

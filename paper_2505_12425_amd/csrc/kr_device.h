@@ -140,6 +140,14 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
     if (OP == OP_RESIZE) {
         resize_axis(x, j.sw, j.dw, x0, wx1, fx);
         resize_axis(y, j.sh, j.dh, y0, wy1, fy);
+    } else if (OP == OP_PERSP) {
+        // binary64 quotients; warp_axis maps a quotient that is not a number
+        // to -2 (fmax ignores it) and clamps infinities
+        const double w = __builtin_fma(j.proj[0], (double)x, __builtin_fma(j.proj[1], (double)y, j.proj[2]));
+        const double xs = __builtin_fma(j.inv[0], (double)x, __builtin_fma(j.inv[1], (double)y, j.inv[2])) / w;
+        const double ys = __builtin_fma(j.inv[3], (double)x, __builtin_fma(j.inv[4], (double)y, j.inv[5])) / w;
+        warp_axis(xs, j.sw, x0, wx1, fx);
+        warp_axis(ys, j.sh, y0, wy1, fy);
     } else {
         const double xs = __builtin_fma(j.inv[0], (double)x, __builtin_fma(j.inv[1], (double)y, j.inv[2]));
         const double ys = __builtin_fma(j.inv[3], (double)x, __builtin_fma(j.inv[4], (double)y, j.inv[5]));

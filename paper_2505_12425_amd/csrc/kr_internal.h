@@ -10,7 +10,7 @@
 
 namespace kr {
 
-enum { OP_RESIZE = 0, OP_WARP = 1 };
+enum { OP_RESIZE = 0, OP_WARP = 1, OP_PERSP = 2 };
 
 // Output/epilogue parameters common to every kernel variant.
 struct Epilogue {
@@ -23,12 +23,14 @@ struct Epilogue {
 };
 
 // One image as the kernels see it.  For warps, inv is the inverse map with
-// its first row and second row kept as given (not pre-scaled).
+// its first row and second row kept as given (not pre-scaled); perspective
+// warps add the inverse homography's third row in proj.
 struct ImageJob {
     const void *src;
     void *dst;
     int sh, sw, dh, dw;
     double inv[6];
+    double proj[3];
 };
 
 // Launchers (resample.hip).  All return the HIP error of the launch.
@@ -38,6 +40,8 @@ hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, con
                          hipStream_t s);
 hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
                        hipStream_t s);
+hipError_t launch_persp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
+                        hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Flip and RGB -> gray (pointops.hip).
 hipError_t launch_flip(int c, kr_dtype t, const void *src, void *dst, int h, int w, int fx, int fy, hipStream_t s);

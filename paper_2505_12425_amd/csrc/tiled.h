@@ -465,6 +465,17 @@ __device__ __forceinline__ double clamp_plain(double X, int n)
     return X < -2.0 ? -2.0 : (X > hi ? hi : X);
 }
 
+// Perspective source coordinate on one axis: num / w in binary64 (correctly
+// rounded); a quotient that is not a number reads as -2; clamped to
+// [-2, n + 1] like the affine coordinates.
+__device__ __forceinline__ double persp_coord(double num, double w, int n)
+{
+    double v = num / w;
+    v = v != v ? -2.0 : v;
+    const double hi = (double)n + 1.0;
+    return v < -2.0 ? -2.0 : (v > hi ? hi : v);
+}
+
 template <int OP, int TW, int TH, bool F32>
 __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const TileGeom &G)
 {
@@ -477,6 +488,7 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
     p.ox1 = min(p.ox0 + TW, j.dw) - 1;
     p.oy1 = min(p.oy0 + TH, j.dh) - 1;
     int x0min, x0max, y0min, y0max;
+    bool persp_ok = true;
     // The four bounds come from four independent evaluations: lane q of the
     // wave computes the q-th one and every lane reads them back (readlane).
     const int q = lane_id() & 3;
@@ -490,6 +502,31 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
         p.inside = x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
         p.by0 = 0;
         p.nslots = 2 * (p.oy1 - p.oy0 + 1);
+    } else if constexpr (OP == OP_PERSP) {
+        // Tap box from the four corners (lane q takes corner q).  Where w > 0
+        // at the corners it is positive over the whole tile, whose image is
+        // then the convex quadrilateral of the corner images; the box gets
+        // one extra pixel on each side for the rounding of the quotients.  A
+        // tile reaching w <= 0 evaluates its pixels from global memory.
+        const double cx = (double)((q & 1) ? p.ox1 : p.ox0), cy = (double)((q & 2) ? p.oy1 : p.oy0);
+        const double w = __builtin_fma(j.proj[0], cx, __builtin_fma(j.proj[1], cy, j.proj[2]));
+        const double X = persp_coord(__builtin_fma(j.inv[0], cx, __builtin_fma(j.inv[1], cy, j.inv[2])), w, W);
+        const double Y = persp_coord(__builtin_fma(j.inv[3], cx, __builtin_fma(j.inv[4], cy, j.inv[5])), w, H);
+        const int ix = (int)__builtin_floor(X), iy = (int)__builtin_floor(Y);
+        const int pos = w > 0.0 ? 1 : 0;
+        persp_ok = (__builtin_amdgcn_readlane(pos, 0) & __builtin_amdgcn_readlane(pos, 1) &
+                    __builtin_amdgcn_readlane(pos, 2) & __builtin_amdgcn_readlane(pos, 3)) != 0;
+        const int a0 = __builtin_amdgcn_readlane(ix, 0), a1 = __builtin_amdgcn_readlane(ix, 1);
+        const int a2 = __builtin_amdgcn_readlane(ix, 2), a3 = __builtin_amdgcn_readlane(ix, 3);
+        const int b0 = __builtin_amdgcn_readlane(iy, 0), b1 = __builtin_amdgcn_readlane(iy, 1);
+        const int b2 = __builtin_amdgcn_readlane(iy, 2), b3 = __builtin_amdgcn_readlane(iy, 3);
+        x0min = min(min(a0, a1), min(a2, a3)) - 1;
+        x0max = max(max(a0, a1), max(a2, a3)) + 1;
+        y0min = min(min(b0, b1), min(b2, b3)) - 1;
+        y0max = max(max(b0, b1), max(b2, b3)) + 1;
+        p.inside = persp_ok && x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
+        p.by0 = y0min;
+        p.nslots = y0max + 2 - y0min;
     } else {
         // Tap box from the four corners (lane q takes corner q).  fma(A, x,
         // fma(B, y, C)) is monotone in x and in y separately, and so are the
@@ -535,7 +572,7 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
     }
     p.bx0 = x0min;
     p.bw = x0max + 2 - x0min;
-    p.direct = p.bw + 2 * KT_MARGIN > G.pitch || p.nslots > G.rows;
+    p.direct = !persp_ok || p.bw + 2 * KT_MARGIN > G.pitch || p.nslots > G.rows;
     p.cx0 = max(p.bx0, 0);
     p.cx1 = min(p.bx0 + p.bw - 1, W - 1);
     p.ng = (p.direct || p.cx0 > p.cx1) ? 0 : ((p.cx1 - p.cx0) >> 4) + 2;
@@ -757,7 +794,9 @@ __device__ __forceinline__ bool layout_aligned(int dw)
         return F32 || C == 4 || (((size_t)dw * C) & 3) == 0;
 }
 
-template <int C, bool F32, class L, bool CLAMP, bool MASK>
+// PERSP: perspective warp (coordinates by persp_coord, always clamped; m is
+// then the unscaled inverse map and the u8 path scales the quotients).
+template <int C, bool F32, class L, bool CLAMP, bool MASK, bool PERSP>
 __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                                const uint32_t *lds)
 {
@@ -767,7 +806,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
     double m[6];
 #pragma unroll
     for (int i = 0; i < 6; i++)
-        m[i] = F32 ? j.inv[i] : t.m2048[i];
+        m[i] = (F32 || PERSP) ? j.inv[i] : t.m2048[i];
     const int pitch = G.pitch;
     const int base = p.by0 * pitch + p.bx0 - KT_MARGIN;
     const bool aligned = layout_aligned<C, F32, L>(j.dw);
@@ -785,6 +824,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
             break;
         const double rowX = __builtin_fma(m[1], (double)y, m[2]);
         const double rowY = __builtin_fma(m[4], (double)y, m[5]);
+        const double rowW = PERSP ? __builtin_fma(j.proj[1], (double)y, j.proj[2]) : 0.0;
 #pragma unroll
         for (int c = 0; c < CPT; c++) {
             const int xr = p.ox0 + c * L::SEG + L::col0();
@@ -792,11 +832,18 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                 uint32_t P[PX];
 #pragma unroll
                 for (int k = 0; k < PX; k++) {
-                    double X = __builtin_fma(m[0], xd[c][k], rowX);
-                    double Y = __builtin_fma(m[3], xd[c][k], rowY);
-                    if (CLAMP) {
-                        X = clamp_scaled(X, W);
-                        Y = clamp_scaled(Y, H);
+                    double X, Y;
+                    if constexpr (PERSP) {
+                        const double wv = __builtin_fma(j.proj[0], xd[c][k], rowW);
+                        X = 2048.0 * persp_coord(__builtin_fma(m[0], xd[c][k], rowX), wv, W);
+                        Y = 2048.0 * persp_coord(__builtin_fma(m[3], xd[c][k], rowY), wv, H);
+                    } else {
+                        X = __builtin_fma(m[0], xd[c][k], rowX);
+                        Y = __builtin_fma(m[3], xd[c][k], rowY);
+                        if (CLAMP) {
+                            X = clamp_scaled(X, W);
+                            Y = clamp_scaled(Y, H);
+                        }
                     }
                     const int Nx = rne_i32(X), Ny = rne_i32(Y);
                     const int x0 = Nx >> 11, y0 = Ny >> 11;
@@ -821,11 +868,18 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                 float o[PX][C];
 #pragma unroll
                 for (int k = 0; k < PX; k++) {
-                    double X = __builtin_fma(m[0], xd[c][k], rowX);
-                    double Y = __builtin_fma(m[3], xd[c][k], rowY);
-                    if (CLAMP) {
-                        X = clamp_plain(X, W);
-                        Y = clamp_plain(Y, H);
+                    double X, Y;
+                    if constexpr (PERSP) {
+                        const double wv = __builtin_fma(j.proj[0], xd[c][k], rowW);
+                        X = persp_coord(__builtin_fma(m[0], xd[c][k], rowX), wv, W);
+                        Y = persp_coord(__builtin_fma(m[3], xd[c][k], rowY), wv, H);
+                    } else {
+                        X = __builtin_fma(m[0], xd[c][k], rowX);
+                        Y = __builtin_fma(m[3], xd[c][k], rowY);
+                        if (CLAMP) {
+                            X = clamp_plain(X, W);
+                            Y = clamp_plain(Y, H);
+                        }
                     }
                     const double fxl = __builtin_floor(X), fyl = __builtin_floor(Y);
                     const int x0 = (int)fxl, y0 = (int)fyl;
@@ -848,16 +902,16 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
     }
 }
 
-template <int C, bool F32, class L>
+template <int C, bool F32, class L, bool PERSP>
 __device__ __forceinline__ void compute_warp(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                              const uint32_t *lds)
 {
     if (p.inside)
-        compute_warp_t<C, F32, L, false, false>(t, p, G, e, lds);
+        compute_warp_t<C, F32, L, false, false, PERSP>(t, p, G, e, lds);
     else if (e.border == KR_BORDER_CONSTANT)
-        compute_warp_t<C, F32, L, true, true>(t, p, G, e, lds);
+        compute_warp_t<C, F32, L, true, true, PERSP>(t, p, G, e, lds);
     else
-        compute_warp_t<C, F32, L, true, false>(t, p, G, e, lds);
+        compute_warp_t<C, F32, L, true, false, PERSP>(t, p, G, e, lds);
 }
 
 template <int C, bool F32, class L, bool MASK>
@@ -1059,18 +1113,20 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
     double m[6];
 #pragma unroll
     for (int i = 0; i < 6; i++)
-        m[i] = F32 ? j.inv[i] : t.m2048[i];
+        m[i] = (F32 || OP == OP_PERSP) ? j.inv[i] : t.m2048[i];
     for (int r = 0; r < L::RPT; r++) {
         const int rr = L::row0() + r * L::ROWS;
         const int y = p.oy0 + rr;
         if (y > p.oy1)
             break;
-        double rowX = 0, rowY = 0;
+        double rowX = 0, rowY = 0, rowW = 0;
         int ry0 = 0;
         uint32_t rw = 0;
-        if constexpr (OP == OP_WARP) {
+        if constexpr (OP != OP_RESIZE) {
             rowX = __builtin_fma(m[1], (double)y, m[2]);
             rowY = __builtin_fma(m[4], (double)y, m[5]);
+            if constexpr (OP == OP_PERSP)
+                rowW = __builtin_fma(j.proj[1], (double)y, j.proj[2]);
         } else {
             ry0 = (int)tab[2 * TW + rr];
             rw = tab[2 * TW + TH + rr];
@@ -1086,7 +1142,23 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
                 int x0, y0;
                 uint32_t wx1, wy1;
                 float fx, fy;
-                if constexpr (OP == OP_WARP) {
+                if constexpr (OP == OP_PERSP) {
+                    const double xd = (double)(p.ox0 + cc);
+                    const double wv = __builtin_fma(j.proj[0], xd, rowW);
+                    const double X = persp_coord(__builtin_fma(m[0], xd, rowX), wv, j.sw);
+                    const double Y = persp_coord(__builtin_fma(m[3], xd, rowY), wv, j.sh);
+                    if constexpr (!F32) {
+                        const int Nx = rne_i32(2048.0 * X), Ny = rne_i32(2048.0 * Y);
+                        x0 = Nx >> 11; y0 = Ny >> 11;
+                        wx1 = (uint32_t)Nx & 2047u; wy1 = (uint32_t)Ny & 2047u;
+                        fx = fy = 0.0f;
+                    } else {
+                        const double fxl = __builtin_floor(X), fyl = __builtin_floor(Y);
+                        x0 = (int)fxl; y0 = (int)fyl;
+                        fx = (float)(X - fxl); fy = (float)(Y - fyl);
+                        wx1 = wy1 = 0;
+                    }
+                } else if constexpr (OP == OP_WARP) {
                     const double xd = (double)(p.ox0 + cc);
                     double X = __builtin_fma(m[0], xd, rowX);
                     double Y = __builtin_fma(m[3], xd, rowY);
@@ -1157,7 +1229,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         else if constexpr (OP == OP_RESIZE)
             compute_resize<C, F32, L>(t, p, G, e, lds);
         else
-            compute_warp<C, F32, L>(t, p, G, e, lds);
+            compute_warp<C, F32, L, OP == OP_PERSP>(t, p, G, e, lds);
         return;
     }
     Prefetch<C, MAXIT> pf;
@@ -1185,7 +1257,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         else if constexpr (OP == OP_RESIZE)
             compute_resize<C, F32, L>(t, p, G, e, lds);
         else
-            compute_warp<C, F32, L>(t, p, G, e, lds);
+            compute_warp<C, F32, L, OP == OP_PERSP>(t, p, G, e, lds);
         if (!more)
             break;
         __syncthreads();

@@ -1,5 +1,6 @@
 // tiled.hip -- per-image launches of the LDS-tiled kernels (tiled.h): tile
 // shape, LDS budget and grid for one image.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -88,9 +89,53 @@ TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th)
 // fall on different banks (gathers).
 static int bank_pitch(int pitch) { return pitch + ((17 - pitch % 32) + 32) % 32; }
 
+// Perspective warp: the largest tap box over the tiles whose corners all have
+// w > 0 and whose box fits the LDS cap (the others evaluate their pixels from
+// global memory), with the device plan's extra pixel per side and one more of
+// slack for its rounding.
+static TileGeom persp_geom(const ImageJob &j, int tw, int th)
+{
+    const int tx_n = (j.dw + tw - 1) / tw, ty_n = (j.dh + th - 1) / th;
+    int maxw = 0, maxh = 0;
+    for (int ty = 0; ty < ty_n; ty++) {
+        for (int tx = 0; tx < tx_n; tx++) {
+            const int x0 = tx * tw, x1 = std::min(x0 + tw, j.dw) - 1;
+            const int y0 = ty * th, y1 = std::min(y0 + th, j.dh) - 1;
+            double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+            bool ok = true;
+            for (int q = 0; q < 4; q++) {
+                const double cx = (q & 1) ? x1 : x0, cy = (q & 2) ? y1 : y0;
+                const double w = j.proj[0] * cx + j.proj[1] * cy + j.proj[2];
+                if (!(w > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                const double X = std::fmin(std::fmax((j.inv[0] * cx + j.inv[1] * cy + j.inv[2]) / w, -2.0), j.sw + 1.0);
+                const double Y = std::fmin(std::fmax((j.inv[3] * cx + j.inv[4] * cy + j.inv[5]) / w, -2.0), j.sh + 1.0);
+                xmin = std::fmin(xmin, X); xmax = std::fmax(xmax, X);
+                ymin = std::fmin(ymin, Y); ymax = std::fmax(ymax, Y);
+            }
+            if (!ok)
+                continue;
+            const int bw = (int)(std::floor(xmax) - std::floor(xmin)) + 6;
+            const int bh = (int)(std::floor(ymax) - std::floor(ymin)) + 6;
+            if ((size_t)bank_pitch(bw + 2 * KT_MARGIN) * bh * 4 + (size_t)(2 * tw + 2 * th) * 4 > KT_LDS_CAP)
+                continue;
+            maxw = std::max(maxw, bw);
+            maxh = std::max(maxh, bh);
+        }
+    }
+    TileGeom G;
+    G.pitch = maxw > 0 ? bank_pitch(maxw + 2 * KT_MARGIN) : 0;
+    G.rows = maxh;
+    return G;
+}
+
 TileGeom tile_geom(const ImageJob &j, int op, int tw, int th)
 {
     TileGeom G;
+    if (op == OP_PERSP)
+        return persp_geom(j, tw, th);
     if (op == OP_WARP) {
         const double ex = std::fabs(j.inv[0]) * (tw - 1) + std::fabs(j.inv[1]) * (th - 1);
         const double ey = std::fabs(j.inv[3]) * (tw - 1) + std::fabs(j.inv[4]) * (th - 1);
@@ -152,7 +197,7 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 #define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
     if (cfg.px == PX && cfg.txt == TXT && cfg.cpt == CPT && cfg.rpt == RPT)                              \
         return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.persistent, gather, fits);
-    if constexpr (OP == OP_WARP) {
+    if constexpr (OP != OP_RESIZE) {
         KR_WARP_CFGS(KR_TRY)
     } else {
         KR_RESIZE_CFGS(KR_TRY)
@@ -180,7 +225,7 @@ static int default_cfgs(int op, bool f32, TileCfg *out)
     };
     // the autotuner's choices on MI355X for 4K sources (3840x2160x3 u8, every
     // source read from HBM): one workgroup per tile beat persistent grids
-    if (op == OP_WARP) {
+    if (op != OP_RESIZE) {
         if (f32) {
             add(1, 64, 1, 8, false);
             add(1, 64, 1, 16, false);
@@ -220,6 +265,13 @@ hipError_t launch_tiled_cfg(int op, int c, kr_dtype dt, const TileCfg &cfg, cons
 {
     const bool f = dt == KR_F32;
     fits = false;
+    if (op == OP_PERSP) {
+        if (c == 3)
+            return f ? launch_shape<OP_PERSP, 3, true>(cfg, j, e, s, false, fits)
+                     : launch_shape<OP_PERSP, 3, false>(cfg, j, e, s, false, fits);
+        return f ? launch_shape<OP_PERSP, 4, true>(cfg, j, e, s, false, fits)
+                 : launch_shape<OP_PERSP, 4, false>(cfg, j, e, s, false, fits);
+    }
     if (op == OP_WARP) {
         if (c == 3)
             return f ? launch_shape<OP_WARP, 3, true>(cfg, j, e, s, false, fits)
@@ -239,6 +291,11 @@ bool tiled_supported(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c ==
 hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
     const bool f = dt == KR_F32;
+    if (op == OP_PERSP) {
+        if (c == 3)
+            return f ? launch_c<OP_PERSP, 3, true>(j, e, s) : launch_c<OP_PERSP, 3, false>(j, e, s);
+        return f ? launch_c<OP_PERSP, 4, true>(j, e, s) : launch_c<OP_PERSP, 4, false>(j, e, s);
+    }
     if (op == OP_WARP) {
         if (c == 3)
             return f ? launch_c<OP_WARP, 3, true>(j, e, s) : launch_c<OP_WARP, 3, false>(j, e, s);

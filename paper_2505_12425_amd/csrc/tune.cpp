@@ -44,7 +44,8 @@ int zclass_of(double px) { return std::max(0, std::min(15, (int)(std::log2(std::
 
 bool known_cfg(const TuneKey &k, const TileCfg &c)
 {
-    if ((k.op != OP_RESIZE && k.op != OP_WARP) || (k.c != 3 && k.c != 4) || (k.f32 != 0 && k.f32 != 1) ||
+    if ((k.op != OP_RESIZE && k.op != OP_WARP && k.op != OP_PERSP) || (k.c != 3 && k.c != 4) ||
+        (k.f32 != 0 && k.f32 != 1) || (k.op == OP_PERSP && k.batch != 0) ||
         (k.batch != 0 && k.batch != 1))
         return false;
     for (const TileCfg &x : k.batch ? batch_candidates(k.op) : image_candidates(k.op))
@@ -152,7 +153,7 @@ void tune_clear()
 std::string tune_key_string(const TuneKey &k)
 {
     char b[128];
-    std::snprintf(b, sizeof b, "%s c=%d %s %s scale=%d size=%d", k.op == OP_WARP ? "warp" : "resize", k.c,
+    std::snprintf(b, sizeof b, "%s c=%d %s %s scale=%d size=%d", k.op == OP_PERSP ? "perspective" : (k.op == OP_WARP ? "warp" : "resize"), k.c,
                   k.f32 ? "f32" : "u8", k.batch ? "batch" : "image", k.sclass, k.zclass);
     return b;
 }
@@ -244,7 +245,7 @@ std::vector<TileCfg> image_candidates(int op)
 #define KR_ADD(PX, TXT, CPT, RPT)                   \
     v.push_back(TileCfg{PX, TXT, CPT, RPT, true});  \
     v.push_back(TileCfg{PX, TXT, CPT, RPT, false});
-    if (op == OP_WARP) {
+    if (op != OP_RESIZE) {
         KR_WARP_CFGS(KR_ADD)
     } else {
         KR_RESIZE_CFGS(KR_ADD)

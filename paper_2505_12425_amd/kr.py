@@ -71,6 +71,10 @@ def lib():
     L.kr_warp_affine.restype = i
     L.kr_resize_nearest.argtypes = [vp, i, i, i, i, vp, i, i, i, npp, vp]
     L.kr_resize_nearest.restype = i
+    L.kr_warp_perspective.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
+    L.kr_warp_perspective.restype = i
+    L.kr_invert_homography.argtypes = [dp, dp]
+    L.kr_invert_homography.restype = i
     L.kr_flip.argtypes = [vp, i, i, i, i, vp, i, i, vp]
     L.kr_flip.restype = i
     L.kr_rgb_to_gray.argtypes = [vp, i, i, i, vp, i, npp, vp]
@@ -222,6 +226,33 @@ def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, bord
     check(lib().kr_warp_affine(sp, sh, sw, c, st, dp_, dh, dw, dt, _m6(m),
                                WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
                                _normalize(mean, std, c), _stream(stream)))
+
+
+def _m9(m):
+    vals = [float(v) for v in (m.reshape(-1).tolist() if hasattr(m, "reshape") else m)]
+    if len(vals) != 9:
+        raise ValueError("homography must have 9 entries")
+    return (ctypes.c_double * 9)(*vals)
+
+
+def warp_perspective(src, dst, m, inverse: bool = False, border: int = CONSTANT, border_value: float = 0.0,
+                     mean=None, std=None, stream=None) -> None:
+    """kr_warp_perspective on torch tensors; m is the row-major 3x3 homography
+    (source->destination unless inverse)."""
+    sp, sh, sw, c, st = _image(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if dc != c:
+        raise ValueError("src and dst channel counts differ")
+    check(lib().kr_warp_perspective(sp, sh, sw, c, st, dp_, dh, dw, dt, _m9(m),
+                                    WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
+                                    _normalize(mean, std, c), _stream(stream)))
+
+
+def invert_homography(m):
+    """kr_invert_homography: the library's inverse of a 3x3 homography."""
+    out = (ctypes.c_double * 9)()
+    check(lib().kr_invert_homography(_m9(m), out))
+    return list(out)
 
 
 def invert_affine(m):

@@ -154,3 +154,17 @@ def serving_requests(n: int, qps: float, seed: int = 0, targets=(224, 384, 512, 
             mt = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0)
         reqs.append(Request(i, float(arrivals[i]), op, h, w, t, t, mt))
     return reqs
+
+
+def random_homography(h: int, w: int, rng: np.random.Generator, jitter: float = 0.15) -> np.ndarray:
+    """Forward (source -> destination) 3x3 homography that moves the four image
+    corners by independent uniform offsets of up to ``jitter`` times the image
+    size (a camera tilt), found from the four correspondences."""
+    src = np.array([[0, 0], [w - 1, 0], [0, h - 1], [w - 1, h - 1]], np.float64)
+    dst = src + rng.uniform(-jitter, jitter, (4, 2)) * np.array([w, h])
+    a, b = [], []
+    for (x, y), (u, v) in zip(src, dst):
+        a.append([x, y, 1, 0, 0, 0, -u * x, -u * y]); b.append(u)
+        a.append([0, 0, 0, x, y, 1, -v * x, -v * y]); b.append(v)
+    p = np.linalg.solve(np.array(a), np.array(b))
+    return np.append(p, 1.0).reshape(3, 3)

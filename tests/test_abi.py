@@ -205,6 +205,7 @@ def test_autotune_table_roundtrip_and_validation():
     kr.autotune_clear()
     assert kr.autotune_save().strip() == "# op c f32 batch sclass zclass px txt cpt rpt persistent"
     good = ("# comment\n"
+            "2 3 0 0 1 11 4 16 1 2 0\n"
             "1 3 0 0 0 11 4 16 1 4 1\n"
             "0 4 1 0 -4 10 1 64 2 4 0\n"
             "1 3 1 1 2 13 4 8 1 1 0\n")
@@ -216,7 +217,8 @@ def test_autotune_table_roundtrip_and_validation():
                 "1 3 0 0 0 11 4 16 1 4 1 9\n",       # trailing field
                 "1 3 0 0 0 11 4 12 1 4 1\n",         # no such configuration
                 "1 3 0 1 0 11 4 16 1 4 1\n",         # batches have no persistent grids
-                "2 3 0 0 0 11 4 16 1 4 1\n",         # unknown op
+                "3 3 0 0 0 11 4 16 1 4 1\n",         # unknown op
+                "2 3 0 1 0 11 4 16 1 2 0\n",         # perspective warps have no batched form
                 "1 2 0 0 0 11 4 16 1 4 1\n",         # channel count without configurations
                 "0 3 0 0 0 11 1 64 2 4 0\nbogus\n"]:  # one bad line rejects the whole text
         with pytest.raises(kr.KrError) as e:
@@ -296,3 +298,28 @@ def test_batch_layout_validation():
     assert L.kr_batch_plan_create_ex(batch_items(), 2, 3, 0, 0, 1, 0.0, None, -1, ctypes.byref(h)) \
         == kr.ERR_INVALID_ARGUMENT
     assert h.value is None
+
+
+def test_invert_homography_matches_oracle_bitwise():
+    rng = np.random.default_rng(17)
+    for _ in range(50):
+        m = wl.random_homography(int(rng.integers(10, 3000)), int(rng.integers(10, 3000)), rng, 0.3)
+        assert kr.invert_homography(m) == list(oracle.invert_homography(m))
+    with pytest.raises(kr.KrError) as e:
+        kr.invert_homography([1, 2, 3, 2, 4, 6, 0, 0, 1])
+    assert e.value.status == kr.ERR_SINGULAR_MATRIX
+    with pytest.raises(kr.KrError):
+        kr.invert_homography([1, 0, 0, 0, 1, 0, 0, 0, math.nan])
+
+
+def test_perspective_validation():
+    L = kr.lib()
+    m = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    f = L.kr_warp_perspective
+    assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, m, 4, 0, 0.0, None, None) == kr.ERR_INVALID_ARGUMENT
+    assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, None, 0, 0, 0.0, None, None) == kr.ERR_INVALID_ARGUMENT
+    sing = (ctypes.c_double * 9)(1, 2, 3, 2, 4, 6, 0, 0, 1)
+    assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, sing, 0, 0, 0.0, None, None) == kr.ERR_SINGULAR_MATRIX
+    nan = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, math.nan)
+    assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, nan, 1, 0, 0.0, None, None) == kr.ERR_SINGULAR_MATRIX
+    assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, m, 0, 0, 300.0, None, None) == kr.ERR_INVALID_ARGUMENT
