@@ -16,7 +16,8 @@ Other workloads: --workload batch (256 mixed-size images -> 224x224 f32
 normalised, one persistent launch, vs per-image launches), --workload warpbatch
 (64 x 1080p warps, graph replay, vs per-image launches), --workload serve
 (continuous-batching request stream; p50/p99 latency), --workload ops
-(nearest-neighbour resize 4K <-> 1080p, flip and RGB -> gray at 4K).
+(nearest-neighbour resize 4K <-> 1080p, flip, RGB -> gray and perspective
+warp at 4K).
 
 Prints ONE JSON line.  Kernel durations come from HIP events recorded around
 every launch on the launch stream; the roofline entry uses the kernel with the
@@ -78,6 +79,32 @@ def nearest_touched_bytes(h, w, dh, dw, c=3, esize=1) -> int:
         return np.unique(((2 * d + 1) * n_in) // (2 * n_out))
     mask = np.zeros((h, w), bool)
     mask[np.ix_(idx(h, dh), idx(w, dw))] = True
+    return _lines_of_pixel_mask(mask, c, esize)
+
+
+def _lib_invert_homography(kr, m):
+    """The library's inverse homography (host call)."""
+    return kr.invert_homography(np.asarray(m).reshape(9))
+
+
+def perspective_touched_bytes(h, w, dh, dw, inv, c=3, esize=1) -> int:
+    """Source bytes (line granular) read by a bilinear perspective warp with
+    inverse homography inv (constant border: out-of-image taps read nothing)."""
+    ys, xs = np.mgrid[0:dh, 0:dw].astype(np.float64)
+    den = inv[6] * xs + inv[7] * ys + inv[8]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sx = (inv[0] * xs + inv[1] * ys + inv[2]) / den
+        sy = (inv[3] * xs + inv[4] * ys + inv[5]) / den
+    sx = np.nan_to_num(np.clip(sx, -2, w + 1), nan=-2.0)
+    sy = np.nan_to_num(np.clip(sy, -2, h + 1), nan=-2.0)
+    x0 = np.floor(sx).astype(np.int64)
+    y0 = np.floor(sy).astype(np.int64)
+    mask = np.zeros((h, w), bool)
+    for dy in (0, 1):
+        for dx in (0, 1):
+            xx, yy = x0 + dx, y0 + dy
+            ok = (xx >= 0) & (xx < w) & (yy >= 0) & (yy < h)
+            mask[yy[ok], xx[ok]] = True
     return _lines_of_pixel_mask(mask, c, esize)
 
 
@@ -451,6 +478,14 @@ def bench_ops(args, torch, kr, wl):
             return lambda s: kr.flip(s, out, True, False)
         return make
 
+    hm = wl.random_homography(2160, 3840, np.random.default_rng(0), 0.12)
+
+    def persp(dt):
+        def make(src):
+            out = torch.empty(src.shape, dtype=dt, device="cuda")
+            return lambda s: kr.warp_perspective(s, out, hm, border=kr.CONSTANT)
+        return make
+
     def gray(dt):
         def make(src):
             out = torch.empty(src.shape[:2] + (1,), dtype=dt, device="cuda")
@@ -467,6 +502,8 @@ def bench_ops(args, torch, kr, wl):
         ("flip_f32", big, big, 12, f32, flip(f32)),
         ("gray_u8", big, big, 1, u8, gray(u8)),
         ("gray_f32", big, big, 4, u8, gray(f32)),
+        ("perspective_u8", big, big, 3, u8, persp(u8)),
+        ("perspective_f32", big, big, 12, u8, persp(f32)),
     ]
     for name, (h, w), (dh, dw), obytes, st, make in cases:
         img = wl.mixed_u8(h, w, 3, seed=0)
@@ -486,8 +523,12 @@ def bench_ops(args, torch, kr, wl):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / reps
         esize = 4 if st == torch.float32 else 1
-        src_bytes = (nearest_touched_bytes(h, w, dh, dw, esize=esize) if name.startswith("nearest")
-                     else h * w * 3 * esize)
+        if name.startswith("nearest"):
+            src_bytes = nearest_touched_bytes(h, w, dh, dw, esize=esize)
+        elif name.startswith("perspective"):
+            src_bytes = perspective_touched_bytes(h, w, dh, dw, _lib_invert_homography(kr, hm))
+        else:
+            src_bytes = h * w * 3 * esize
         alg = src_bytes + dh * dw * obytes
         gbps = alg / (ms * 1e-3) / 1e9
         kern[name] = {"avg_us": round(ms * 1e3, 3), "alg_bytes": alg, "GBps": round(gbps, 1),
@@ -499,7 +540,8 @@ def bench_ops(args, torch, kr, wl):
     dom = max(kern, key=lambda n: kern[n]["avg_us"])
     k = kern[dom]
     return {
-        "metric": "output Gpixels/s (nearest resize 4K <-> 1080p, flip and RGB->gray at 4K, u8 and f32 outputs)",
+        "metric": "output Gpixels/s (nearest resize 4K <-> 1080p, flip, RGB->gray and perspective warp at 4K, "
+                  "u8 and f32 outputs)",
         "value": round(total_px / (total_ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(total_ms, 4),
         "config": {"workload": "ops: 3840x2160x3 u8 (f32 for the f32 flip) and 1920x1080x3 u8 sources, "
                                "one launch of each operator per step, cold sources", "px_per_step": total_px},
