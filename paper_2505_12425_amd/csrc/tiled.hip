@@ -1,6 +1,7 @@
 // tiled.hip -- per-image launches of the LDS-tiled kernels (tiled.h): tile
 // shape, LDS budget and grid for one image.
 #include <algorithm>
+#include <vector>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -93,36 +94,122 @@ static int bank_pitch(int pitch) { return pitch + ((17 - pitch % 32) + 32) % 32;
 // w > 0 and whose box fits the LDS cap (the others evaluate their pixels from
 // global memory), with the device plan's extra pixel per side and one more of
 // slack for its rounding.
+//
+// Scanning every tile costs four quotient pairs per tile on the host, more
+// than the kernel itself at 4K.  The tiles are therefore grouped into regions
+// (at most 16 x 16), each region gets an upper bound on its tiles' boxes, and
+// only regions whose bound could raise the running maximum are scanned.  The
+// bound is the smaller of two: the span of the region's own clamped corner
+// images (the image of a rectangle on which w > 0 is the convex quadrilateral
+// of its corner images, and the clamp is monotone), and the mean-value bound
+// sup|dX/dx| (tw - 1) + sup|dX/dy| (th - 1).  For X = (a x + b y + c) / w with
+// w = g x + h y + i, dX/dx = ((a h - g b) y + (a i - g c)) / w^2 and dX/dy =
+// ((b g - h a) x + (b i - h c)) / w^2: affine numerators, largest in size at
+// the region's corners, over the smallest w there.  The result equals the
+// full scan's.
+struct PerspBox {
+    int bw, bh;  // -1: some corner has w <= 0
+};
+
+static inline double clamp_coord(double v, double hi)
+{
+    v = v != v ? -2.0 : v;
+    return v < -2.0 ? -2.0 : (v > hi ? hi : v);
+}
+
+// Tap box of the output rectangle [x0, x1] x [y0, y1] from its corners.
+static PerspBox corner_box(const ImageJob &j, double x0, double x1, double y0, double y1)
+{
+    const double hx = j.sw + 1.0, hy = j.sh + 1.0;
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int q = 0; q < 4; q++) {
+        const double cx = (q & 1) ? x1 : x0, cy = (q & 2) ? y1 : y0;
+        const double w = j.proj[0] * cx + j.proj[1] * cy + j.proj[2];
+        if (!(w > 0.0))
+            return {-1, -1};
+        const double X = clamp_coord((j.inv[0] * cx + j.inv[1] * cy + j.inv[2]) / w, hx);
+        const double Y = clamp_coord((j.inv[3] * cx + j.inv[4] * cy + j.inv[5]) / w, hy);
+        xmin = X < xmin ? X : xmin;
+        xmax = X > xmax ? X : xmax;
+        ymin = Y < ymin ? Y : ymin;
+        ymax = Y > ymax ? Y : ymax;
+    }
+    return {(int)(std::floor(xmax) - std::floor(xmin)), (int)(std::floor(ymax) - std::floor(ymin))};
+}
+
 static TileGeom persp_geom(const ImageJob &j, int tw, int th)
 {
     const int tx_n = (j.dw + tw - 1) / tw, ty_n = (j.dh + th - 1) / th;
-    int maxw = 0, maxh = 0;
-    for (int ty = 0; ty < ty_n; ty++) {
-        for (int tx = 0; tx < tx_n; tx++) {
-            const int x0 = tx * tw, x1 = std::min(x0 + tw, j.dw) - 1;
-            const int y0 = ty * th, y1 = std::min(y0 + th, j.dh) - 1;
-            double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-            bool ok = true;
+    const int rtx = (tx_n + 15) / 16, rty = (ty_n + 15) / 16;  // tiles per region
+    const double a = j.inv[0], b = j.inv[1], c = j.inv[2], d = j.inv[3], e = j.inv[4], f = j.inv[5];
+    const double g = j.proj[0], h = j.proj[1], i = j.proj[2];
+    const double hx = j.sw + 1.0, hy = j.sh + 1.0;
+    struct Region {
+        int tx0, tx1, ty0, ty1;  // tile range, half-open
+        double ux, uy;           // bounds on the tiles' corner-image spans
+    };
+    std::vector<Region> regs;
+    for (int ry = 0; ry < ty_n; ry += rty) {
+        for (int rx = 0; rx < tx_n; rx += rtx) {
+            Region r{rx, std::min(rx + rtx, tx_n), ry, std::min(ry + rty, ty_n), 1e300, 1e300};
+            const double X0 = (double)rx * tw, X1 = (double)(std::min(r.tx1 * tw, j.dw) - 1);
+            const double Y0 = (double)ry * th, Y1 = (double)(std::min(r.ty1 * th, j.dh) - 1);
+            double wmin = 1e300, xlo = 1e300, xhi = -1e300, ylo = 1e300, yhi = -1e300;
+            bool pos = true;
             for (int q = 0; q < 4; q++) {
-                const double cx = (q & 1) ? x1 : x0, cy = (q & 2) ? y1 : y0;
-                const double w = j.proj[0] * cx + j.proj[1] * cy + j.proj[2];
-                if (!(w > 0.0)) {
-                    ok = false;
-                    break;
+                const double cx = (q & 1) ? X1 : X0, cy = (q & 2) ? Y1 : Y0;
+                const double w = g * cx + h * cy + i;
+                pos = pos && w > 0.0;
+                wmin = w < wmin ? w : wmin;
+                if (pos) {
+                    const double X = clamp_coord((a * cx + b * cy + c) / w, hx);
+                    const double Y = clamp_coord((d * cx + e * cy + f) / w, hy);
+                    xlo = X < xlo ? X : xlo;
+                    xhi = X > xhi ? X : xhi;
+                    ylo = Y < ylo ? Y : ylo;
+                    yhi = Y > yhi ? Y : yhi;
                 }
-                const double X = std::fmin(std::fmax((j.inv[0] * cx + j.inv[1] * cy + j.inv[2]) / w, -2.0), j.sw + 1.0);
-                const double Y = std::fmin(std::fmax((j.inv[3] * cx + j.inv[4] * cy + j.inv[5]) / w, -2.0), j.sh + 1.0);
-                xmin = std::fmin(xmin, X); xmax = std::fmax(xmax, X);
-                ymin = std::fmin(ymin, Y); ymax = std::fmax(ymax, Y);
             }
-            if (!ok)
-                continue;
-            const int bw = (int)(std::floor(xmax) - std::floor(xmin)) + 6;
-            const int bh = (int)(std::floor(ymax) - std::floor(ymin)) + 6;
-            if ((size_t)bank_pitch(bw + 2 * KT_MARGIN) * bh * 4 + (size_t)(2 * tw + 2 * th) * 4 > KT_LDS_CAP)
-                continue;
-            maxw = std::max(maxw, bw);
-            maxh = std::max(maxh, bh);
+            if (pos) {
+                auto amax = [](double p, double q) { return std::fabs(p) > std::fabs(q) ? std::fabs(p) : std::fabs(q); };
+                const double w2 = wmin * wmin;
+                const double sxx = amax((a * h - g * b) * Y0 + (a * i - g * c), (a * h - g * b) * Y1 + (a * i - g * c));
+                const double sxy = amax((b * g - h * a) * X0 + (b * i - h * c), (b * g - h * a) * X1 + (b * i - h * c));
+                const double syx = amax((d * h - g * e) * Y0 + (d * i - g * f), (d * h - g * e) * Y1 + (d * i - g * f));
+                const double syy = amax((e * g - h * d) * X0 + (e * i - h * f), (e * g - h * d) * X1 + (e * i - h * f));
+                const double mx = (sxx * (tw - 1) + sxy * (th - 1)) / w2;
+                const double my = (syx * (tw - 1) + syy * (th - 1)) / w2;
+                // relative and absolute margins cover the rounding of the bound
+                r.ux = std::min(mx, xhi - xlo) * (1.0 + 1e-9) + 1e-6;
+                r.uy = std::min(my, yhi - ylo) * (1.0 + 1e-9) + 1e-6;
+                r.ux = r.ux == r.ux ? r.ux : 1e300;  // w^2 underflow: no bound
+                r.uy = r.uy == r.uy ? r.uy : 1e300;
+            }
+            regs.push_back(r);
+        }
+    }
+    // regions with the largest bounds first, so the running maximum rises early
+    std::sort(regs.begin(), regs.end(),
+              [](const Region &p, const Region &q) { return p.ux + p.uy > q.ux + q.uy; });
+    int maxw = 0, maxh = 0;
+    for (const Region &r : regs) {
+        // floor(p) - floor(q) <= ceil(p - q): a region whose bound cannot beat
+        // both maxima has no tile that would change them
+        if (maxw > 0 && std::ceil(r.ux) + 6.0 <= (double)maxw && std::ceil(r.uy) + 6.0 <= (double)maxh)
+            continue;
+        for (int ty = r.ty0; ty < r.ty1; ty++) {
+            for (int tx = r.tx0; tx < r.tx1; tx++) {
+                const int x0 = tx * tw, x1 = std::min(x0 + tw, j.dw) - 1;
+                const int y0 = ty * th, y1 = std::min(y0 + th, j.dh) - 1;
+                const PerspBox bx = corner_box(j, x0, x1, y0, y1);
+                if (bx.bw < 0)
+                    continue;
+                const int bw = bx.bw + 6, bh = bx.bh + 6;
+                if ((size_t)bank_pitch(bw + 2 * KT_MARGIN) * bh * 4 + (size_t)(2 * tw + 2 * th) * 4 > KT_LDS_CAP)
+                    continue;
+                maxw = std::max(maxw, bw);
+                maxh = std::max(maxh, bh);
+            }
         }
     }
     TileGeom G;

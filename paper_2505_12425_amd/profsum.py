@@ -41,35 +41,59 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-_TPL = re.compile(r"kr::k_(tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+>")
+_TPL = re.compile(r"kr::k_(tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"
+                  r"(?:, (?:true|false))?>")
+_OPS = {"0": "resize", "1": "warp", "2": "perspective"}
+_POINT = re.compile(r"kr::(?:\(anonymous namespace\)::)?k_(nearest|flip_u8|flip_f32|gray)<([^>]*)>")
+
+
+def _short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").split("(")[0]
 
 
 def label(name: str) -> str:
-    """Readable label: e.g. 'warp_u8 c3 tiled 4x16x1x4' for a k_tiled instance."""
+    """Readable label: e.g. 'warp_u8 c3 4x16x1x4' for a k_tiled instance."""
     m = _TPL.search(name)
     if m:
         kind, op, c, f32, px, txt, cpt, rpt = m.groups()
-        opn = "warp" if op == "1" else "resize"
         dt = "f32" if f32 == "true" else "u8"
         pre = "batch_" if kind == "batch" else ""
-        return f"{pre}{opn}_{dt} c{c} {px}x{txt}x{cpt}x{rpt}"
+        return f"{pre}{_OPS[op]}_{dt} c{c} {px}x{txt}x{cpt}x{rpt}"
     if "k_copy" in name:
         return "copy"
     if "k_generic" in name:
-        return "generic " + name.split("(")[0].split("k_generic")[-1]
-    return name.split("(")[0][:60]
+        return "generic " + _short(name).split("k_generic")[-1]
+    m = _POINT.search(name)
+    if m:
+        return f"{m.group(1)}<{m.group(2)}>"
+    return _short(name)[:60]
+
+
+def _point_key(kind: str, args: str) -> str | None:
+    a = [t.strip() for t in args.split(",")]
+    if kind in ("flip_u8", "flip_f32"):
+        return kind if a[0] == "3" else None
+    if kind == "gray":  # <SRC_F32, DST_F32>
+        return None if a[0] == "true" else ("gray_f32" if a[1] == "true" else "gray_u8")
+    # nearest <C, SRC_F32, DST_F32>; the direction is told apart by grid size
+    if a[0] != "3" or a[1] == "true":
+        return None
+    return "nearest_{}_" + ("f32" if a[2] == "true" else "u8")
 
 
 def bench_key(name: str) -> str | None:
-    """The benchmark's name for a kernel ('warp_f32', 'batch_resize_f32', ...)."""
+    """The benchmark's name for a kernel ('warp_f32', 'batch_resize_f32', ...).
+    Nearest-resize kernels give a pattern with '{}' for the direction."""
     m = _TPL.search(name)
     if not m:
-        return "copy" if "k_copy" in name else None
+        if "k_copy" in name:
+            return "copy"
+        p = _POINT.search(name)
+        return _point_key(*p.groups()) if p else None
     kind, op, c, f32 = m.groups()[:4]
     if c != "3":
         return None
-    return ("batch_" if kind == "batch" else "") + ("warp" if op == "1" else "resize") + \
-        ("_f32" if f32 == "true" else "_u8")
+    return ("batch_" if kind == "batch" else "") + _OPS[op] + ("_f32" if f32 == "true" else "_u8")
 
 
 def _one(pattern: str) -> str:
@@ -90,46 +114,79 @@ def stats(dir_: str, out: str, cmd: str) -> None:
             label(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
     lines += ["", "Full kernel names:", ""]
-    lines += [f"- `{label(r['Name'])}`: `{r['Name'].split('(')[0]}`" for r in rows]
+    lines += [f"- `{label(r['Name'])}`: `{_short(r['Name'])}`" for r in rows]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
 
 def _counter_means(dir_: str, counter: str):
+    """Mean counter value per (kernel, grid size), with the dispatch count."""
     path = _one(os.path.join(dir_, "**", "*counter_collection.csv"))
     acc = defaultdict(list)
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+            acc[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    out = {}
+    for k, v in acc.items():
+        if bench_key(k[0]) == "copy":
+            # copies of several sizes share one grid; the calibration copy is
+            # the largest, so keep the dispatches within 2x of the biggest
+            top = max(v)
+            v = [x for x in v if x >= 0.5 * top]
+        out[k] = (sum(v) / len(v), len(v))
+    return out
+
+
+def _keyed(means):
+    """Benchmark key -> the (kernel, grid) entries it covers.  A per-image key
+    takes the entry with the most dispatches; a batch key ('batch_...') takes
+    every entry, since one batch launches one kernel per group and the groups
+    together make one step.  A nearest kernel seen at two grid sizes is the
+    downscale at the smaller grid and the upscale at the larger."""
+    grids = defaultdict(set)
+    for (name, grid) in means:
+        grids[name].add(grid)
+    sel = defaultdict(list)
+    for (name, grid), (_, n) in means.items():
+        key = bench_key(name)
+        if key is None:
+            continue
+        if "{}" in key:
+            g = sorted(grids[name])
+            if len(g) != 2:
+                continue
+            key = key.format("down" if grid == g[0] else "up")
+        if key.startswith("batch_"):
+            sel[key].append((name, grid))
+        elif not sel[key] or n > means[sel[key][0]][1]:
+            sel[key] = [(name, grid)]
+    return dict(sel)
 
 
 def traffic(fetch_dir, write_dir, copy_bytes, out, md, cmd_fetch, cmd_write, only=None) -> None:
     fetch = _counter_means(fetch_dir, "FETCH_SIZE")
     write = _counter_means(write_dir, "WRITE_SIZE")
-    copy_f = [v for k, v in fetch.items() if bench_key(k) == "copy"]
-    copy_w = [v for k, v in write.items() if bench_key(k) == "copy"]
-    if not copy_f or not copy_w:
+    fkeys, wkeys = _keyed(fetch), _keyed(write)
+    if "copy" not in fkeys or "copy" not in wkeys:
         raise SystemExit("the profiled run has no copy-kernel dispatch to calibrate against")
-    f_fac = copy_bytes / (copy_f[0][0] * 1024.0)
-    w_fac = copy_bytes / (copy_w[0][0] * 1024.0)
-    # per benchmark kernel: the instantiation with the most dispatches
-    best = {}
-    for name, (fk, n) in fetch.items():
-        key = bench_key(name)
-        if key in (None, "copy") or name not in write or (only and key not in only):
-            continue
-        if key not in best or n > best[key][1]:
-            best[key] = (name, n)
+    copy_f, copy_w = fetch[fkeys["copy"][0]], write[wkeys["copy"][0]]
+    f_fac = copy_bytes / (copy_f[0] * 1024.0)
+    w_fac = copy_bytes / (copy_w[0] * 1024.0)
     kernels = {}
-    for key, (name, n) in sorted(best.items()):
-        fk, wk = fetch[name][0], write[name][0]
-        kernels[key] = {"kernel": label(name), "dispatches": n, "fetch_kib": round(fk, 1),
+    for key in sorted(fkeys):
+        if key == "copy" or key not in wkeys or (only and key not in only):
+            continue
+        fk = sum(fetch[e][0] for e in fkeys[key])
+        wk = sum(write[e][0] for e in wkeys[key])
+        n = min(fetch[e][1] for e in fkeys[key])
+        kernels[key] = {"kernel": " + ".join(label(e[0]) for e in fkeys[key]),
+                        "grid": [e[1] for e in fkeys[key]], "dispatches": n,
+                        "fetch_kib": round(fk, 1),
                         "write_kib": round(wk, 1), "fetch_bytes": round(fk * 1024 * f_fac),
                         "write_bytes": round(wk * 1024 * w_fac),
                         "bytes_per_launch": round(fk * 1024 * f_fac + wk * 1024 * w_fac)}
-    calib = {"copy_bytes_each_way": copy_bytes, "fetch_kib_per_copy": round(copy_f[0][0], 1),
-             "write_kib_per_copy": round(copy_w[0][0], 1), "fetch_factor": round(f_fac, 4),
+    calib = {"copy_bytes_each_way": copy_bytes, "fetch_kib_per_copy": round(copy_f[0], 1),
+             "write_kib_per_copy": round(copy_w[0], 1), "fetch_factor": round(f_fac, 4),
              "write_factor": round(w_fac, 4)}
     for k in kernels.values():
         k.update(command_fetch=cmd_fetch, command_write=cmd_write, calibration=calib)
@@ -147,7 +204,7 @@ def traffic(fetch_dir, write_dir, copy_bytes, out, md, cmd_fetch, cmd_write, onl
         lines = ["# HBM traffic per launch (rocprofv3 --pmc)", "", "Commands:", "", "```", cmd_fetch, cmd_write,
                  "```", "",
                  f"Calibration: the copy kernel moves {copy_bytes} B each way per dispatch; FETCH_SIZE reads "
-                 f"{copy_f[0][0]:.1f} KiB (factor {f_fac:.4f}), WRITE_SIZE {copy_w[0][0]:.1f} KiB "
+                 f"{copy_f[0]:.1f} KiB (factor {f_fac:.4f}), WRITE_SIZE {copy_w[0]:.1f} KiB "
                  f"(factor {w_fac:.4f}).", "",
                  "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | written MB | total MB |",
                  "|---|---:|---:|---:|---:|---:|---:|"]

@@ -1,0 +1,61 @@
+"""Host logic of the rocprofv3 summariser: kernel labels, benchmark keys and
+the HBM-traffic calibration, on small synthetic counter files."""
+import csv
+import json
+import os
+
+from paper_2505_12425_amd import profsum
+
+TILED_W = "void kr::k_tiled<1, 3, true, 1, 64, 1, 16, 3, true>(kr::TiledJob, kr::Epilogue, kr::TileGeom)"
+TILED_P = "void kr::k_tiled<2, 3, false, 4, 16, 1, 4, 3, false>(kr::TiledJob, kr::Epilogue, kr::TileGeom)"
+BATCH_A = "void kr::k_batch<1, 3, false, 4, 16, 1, 2, 3>(kr::TiledJob const*, int, int)"
+BATCH_B = "void kr::k_batch<1, 3, false, 4, 8, 1, 1, 3>(kr::TiledJob const*, int, int)"
+NEAR = "void kr::(anonymous namespace)::k_nearest<3, false, true>(kr::NearestJob, kr::Epilogue)"
+GRAY = "void kr::(anonymous namespace)::k_gray<false, false>(void const*, void*, int)"
+COPY = "kr::k_copy(unsigned int __vector(4)*, unsigned int __vector(4) const*, unsigned long)"
+
+
+def test_labels_and_keys():
+    assert profsum.label(TILED_W) == "warp_f32 c3 1x64x1x16"
+    assert profsum.label(TILED_P) == "perspective_u8 c3 4x16x1x4"
+    assert profsum.label(BATCH_A) == "batch_warp_u8 c3 4x16x1x2"
+    assert profsum.label(COPY) == "copy"
+    assert profsum.label(NEAR) == "nearest<3, false, true>"
+    assert profsum.bench_key(TILED_W) == "warp_f32"
+    assert profsum.bench_key(TILED_P) == "perspective_u8"
+    assert profsum.bench_key(BATCH_B) == "batch_warp_u8"
+    assert profsum.bench_key(GRAY) == "gray_u8"
+    assert profsum.bench_key(NEAR) == "nearest_{}_f32"
+    assert profsum.bench_key(TILED_W.replace("<1, 3,", "<1, 4,")) is None  # only 3-channel kernels are benchmarked
+
+
+def _write(path, counter, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "r_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        for name, grid, val in rows:
+            w.writerow([name, grid, counter, val])
+
+
+def test_traffic_calibration_and_grouping(tmp_path):
+    gib = 1 << 30
+    # FETCH_SIZE reads half the bytes on the copy, WRITE_SIZE all of them;
+    # a 100 MiB copy on the same grid must not enter the calibration
+    fetch = [(COPY, 524288, gib / 2048), (COPY, 524288, gib / 2048), (COPY, 524288, 100 * 2 ** 20 / 2048),
+             (BATCH_A, 1000, 300.0), (BATCH_B, 500, 100.0),
+             (NEAR, 1000, 10.0), (NEAR, 4000, 20.0), (GRAY, 64, 7.0)]
+    write = [(COPY, 524288, gib / 1024), (COPY, 524288, gib / 1024), (COPY, 524288, 100 * 2 ** 20 / 1024),
+             (BATCH_A, 1000, 400.0), (BATCH_B, 500, 50.0),
+             (NEAR, 1000, 30.0), (NEAR, 4000, 120.0), (GRAY, 64, 8.0)]
+    _write(tmp_path / "f", "FETCH_SIZE", fetch)
+    _write(tmp_path / "w", "WRITE_SIZE", write)
+    out = tmp_path / "t.json"
+    profsum.traffic(str(tmp_path / "f"), str(tmp_path / "w"), gib, str(out), str(tmp_path / "t.md"), "cf", "cw")
+    k = json.load(open(out))["kernels"]
+    assert k["batch_warp_u8"]["fetch_bytes"] == 2 * 400 * 1024  # both groups of the batch, factor 2
+    assert k["batch_warp_u8"]["write_bytes"] == 450 * 1024
+    assert k["nearest_down_f32"]["bytes_per_launch"] == (2 * 10 + 30) * 1024  # smaller grid
+    assert k["nearest_up_f32"]["bytes_per_launch"] == (2 * 20 + 120) * 1024
+    assert k["gray_u8"]["bytes_per_launch"] == (2 * 7 + 8) * 1024
+    assert k["gray_u8"]["calibration"]["fetch_factor"] == 2.0
