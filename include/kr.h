@@ -10,7 +10,8 @@
  * The paper prints no resampling formula; the definitions fixed here are:
  *
  *  - layout: HWC-contiguous, C interleaved channels (1 <= C <= 4), row pitch
- *    W*C elements, u8 or f32 samples;
+ *    W*C elements (sources may also be views with a larger pitch, see the
+ *    *_view entry points), u8 or f32 samples;
  *  - half-pixel centres: resize source x = (dx + 1/2) * W_in / W_out - 1/2,
  *    evaluated exactly as a rational; warp destination pixel (x, y) maps to
  *    xs = fma(A, x, fma(B, y, C)), ys = fma(D, x, fma(E, y, F)) in binary64,
@@ -162,8 +163,47 @@ kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_d
  */
 kr_status kr_invert_homography(const double m[9], double inv[9]);
 
+/*
+ * Source views (zero-copy crops and slices of a larger image, Sec. II-B.3):
+ * the same operators reading a source whose rows are src_pitch BYTES apart
+ * instead of src_w * c elements.  src points at the view's first pixel; pixel
+ * (x, y) of the view starts at src + y * src_pitch + x * c * elem_size.
+ *  - src_pitch = 0 means contiguous and is the plain entry point (src then
+ *    16-byte aligned as usual);
+ *  - otherwise src_pitch must be a whole number of pixels (c * elem_size
+ *    bytes) and at least one row (src_w * c * elem_size), and src must lie a
+ *    whole number of pixels past a 16-byte boundary: any pixel-aligned view
+ *    into a 16-byte-aligned buffer qualifies (KR_ERR_INVALID_ARGUMENT else);
+ *  - the view may span at most 2^31 - 32 pixels of its buffer, counted from
+ *    the 16-byte boundary at or below src;
+ *  - bytes read: the view's pixels, the bytes between its rows that the
+ *    kernels' 16-byte row loads cover, and at most the aligned dwords that
+ *    hold its first and last bytes; nothing before the dword holding the
+ *    first byte or after the dword holding the last one;
+ *  - dst is written exactly as by the plain entry point; it must not overlap
+ *    the source's span (first to last byte, pitch included).
+ * The output equals the plain entry point's on a contiguous copy of the view,
+ * bit for bit.
+ */
+kr_status kr_resize_bilinear_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                                  void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                                  kr_border border, float border_value, const kr_normalize *norm, void *stream);
+kr_status kr_warp_affine_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                              void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                              const double m[6], int flags,
+                              kr_border border, float border_value, const kr_normalize *norm, void *stream);
+kr_status kr_warp_perspective_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                                   void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                                   const double m[9], int flags,
+                                   kr_border border, float border_value, const kr_normalize *norm, void *stream);
+kr_status kr_resize_nearest_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                                 void *dst, int dst_h, int dst_w, kr_dtype dst_t,
+                                 const kr_normalize *norm, void *stream);
+
 /* One image of a batch.  op: 0 = resize, 1 = warp.  m and flags are read for
- * warps only (same meaning as in kr_warp_affine). */
+ * warps only (same meaning as in kr_warp_affine).  src_pitch: bytes between
+ * source rows, 0 for a contiguous source, else a view with the rules of
+ * kr_resize_bilinear_view. */
 typedef struct {
     int op;
     const void *src;
@@ -172,6 +212,7 @@ typedef struct {
     int dst_h, dst_w;
     double m[6];
     int flags;
+    size_t src_pitch;
 } kr_batch_item;
 
 #define KR_OP_RESIZE 0

@@ -4,6 +4,7 @@
 // Compiled with -ffp-contract=off: kr_invert_affine's formula must round each
 // product and sum on its own, exactly as written.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -41,8 +42,58 @@ kr_status check_image(const char *what, const void *p, int h, int w, int c)
     return KR_OK;
 }
 
+int view_shift(const void *src, size_t px_bytes)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src);
+    for (int k = 0; k < 16; k++)
+        if (((a - (uintptr_t)k * px_bytes) & 15) == 0)
+            return k;
+    return -1;
+}
+
+kr_status check_source(const void *src, int h, int w, int c, kr_dtype st, size_t pitch)
+{
+    if (pitch == 0)
+        return check_image("src", src, h, w, c);
+    if (!src)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src pointer is NULL");
+    if (h < 1 || w < 1 || h > KR_MAX_DIM || w > KR_MAX_DIM)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src size %dx%d outside [1, %d]", h, w, KR_MAX_DIM);
+    const size_t px = (size_t)c * elem_size(st);
+    if (view_shift(src, px) < 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src view does not start a whole number of pixels past a 16-byte boundary");
+    if (pitch < (size_t)w * px || pitch % px != 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src pitch %zu is not a whole number of pixels >= the row's %zu bytes",
+                    pitch, (size_t)w * px);
+    if (15 + (size_t)(h - 1) * (pitch / px) + (size_t)w > (size_t)INT32_MAX - 16)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src view spans more than 2^31 - 32 pixels");
+    return KR_OK;
+}
+
+void set_source(ImageJob &j, const void *src, int h, int w, int c, kr_dtype st, size_t pitch)
+{
+    j.sh = h;
+    j.sw = w;
+    if (pitch == 0) {
+        j.src = src;
+        j.sp = w;
+        j.sk = 0;
+        return;
+    }
+    const size_t px = (size_t)c * elem_size(st);
+    j.sk = view_shift(src, px);
+    j.sp = (int)(pitch / px);
+    j.src = static_cast<const uint8_t *>(src) - (size_t)j.sk * px;
+}
+
+size_t source_span(int h, int w, int c, kr_dtype st, size_t pitch)
+{
+    const size_t row = (size_t)w * (size_t)c * elem_size(st);
+    return (size_t)(h - 1) * (pitch ? pitch : row) + row;
+}
+
 kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void *dst, int dh, int dw,
-                       kr_dtype dt, kr_border border, float bval, const kr_normalize *norm)
+                       kr_dtype dt, kr_border border, float bval, const kr_normalize *norm, size_t src_pitch)
 {
     if (c < 1 || c > 4)
         return fail(KR_ERR_UNSUPPORTED, "channel count %d not in [1, 4]", c);
@@ -50,7 +101,7 @@ kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void
         return fail(KR_ERR_UNSUPPORTED, "dtype pair (%d -> %d) not supported", (int)st, (int)dt);
     if (border != KR_BORDER_CONSTANT && border != KR_BORDER_REPLICATE)
         return fail(KR_ERR_UNSUPPORTED, "border mode %d not supported", (int)border);
-    kr_status s = check_image("src", src, sh, sw, c);
+    kr_status s = check_source(src, sh, sw, c, st, src_pitch);
     if (s != KR_OK)
         return s;
     s = check_image("dst", dst, dh, dw, c);
@@ -68,7 +119,7 @@ kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void
                 return fail(KR_ERR_INVALID_ARGUMENT, "normalisation channel %d has a bad mean/std", i);
     }
     const uintptr_t s0 = reinterpret_cast<uintptr_t>(src);
-    const uintptr_t s1 = s0 + (uintptr_t)sh * (uintptr_t)sw * (uintptr_t)c * elem_size(st);
+    const uintptr_t s1 = s0 + source_span(sh, sw, c, st, src_pitch);
     const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst);
     const uintptr_t d1 = d0 + (uintptr_t)dh * (uintptr_t)dw * (uintptr_t)c * elem_size(dt);
     if (s0 < d1 && d0 < s1)
@@ -143,17 +194,19 @@ using namespace kr;
 
 extern "C" {
 
-kr_status kr_resize_bilinear(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
-                             int dst_h, int dst_w, kr_dtype dst_t, kr_border border, float border_value,
-                             const kr_normalize *norm, void *stream)
+kr_status kr_resize_bilinear_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                                  void *dst, int dst_h, int dst_w, kr_dtype dst_t, kr_border border,
+                                  float border_value, const kr_normalize *norm, void *stream)
 {
     clear_error();
-    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm,
+                               src_pitch);
     if (s != KR_OK)
         return s;
     ImageJob j;
     std::memset(&j, 0, sizeof j);
-    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    set_source(j, src, src_h, src_w, c, src_t, src_pitch);
+    j.dst = dst; j.dh = dst_h; j.dw = dst_w;
     const Epilogue e = make_epilogue(c, border, border_value, norm);
     const hipError_t err = launch_resize(c, src_t, dst_t, j, e, (hipStream_t)stream);
     if (err != hipSuccess)
@@ -161,12 +214,21 @@ kr_status kr_resize_bilinear(const void *src, int src_h, int src_w, int c, kr_dt
     return KR_OK;
 }
 
-kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
-                         int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags,
-                         kr_border border, float border_value, const kr_normalize *norm, void *stream)
+kr_status kr_resize_bilinear(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
+                             int dst_h, int dst_w, kr_dtype dst_t, kr_border border, float border_value,
+                             const kr_normalize *norm, void *stream)
+{
+    return kr_resize_bilinear_view(src, src_h, src_w, 0, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value,
+                                   norm, stream);
+}
+
+kr_status kr_warp_affine_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                              void *dst, int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags,
+                              kr_border border, float border_value, const kr_normalize *norm, void *stream)
 {
     clear_error();
-    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm,
+                               src_pitch);
     if (s != KR_OK)
         return s;
     if (flags & ~KR_WARP_INVERSE_MAP)
@@ -176,7 +238,8 @@ kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype 
     s = check_matrix(m, flags, j.inv);
     if (s != KR_OK)
         return s;
-    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    set_source(j, src, src_h, src_w, c, src_t, src_pitch);
+    j.dst = dst; j.dh = dst_h; j.dw = dst_w;
     const Epilogue e = make_epilogue(c, border, border_value, norm);
     const hipError_t err = launch_warp(c, src_t, dst_t, j, e, (hipStream_t)stream);
     if (err != hipSuccess)
@@ -184,22 +247,38 @@ kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype 
     return KR_OK;
 }
 
-kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst, int dst_h,
-                            int dst_w, kr_dtype dst_t, const kr_normalize *norm, void *stream)
+kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
+                         int dst_h, int dst_w, kr_dtype dst_t, const double m[6], int flags,
+                         kr_border border, float border_value, const kr_normalize *norm, void *stream)
+{
+    return kr_warp_affine_view(src, src_h, src_w, 0, c, src_t, dst, dst_h, dst_w, dst_t, m, flags, border,
+                               border_value, norm, stream);
+}
+
+kr_status kr_resize_nearest_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                                 void *dst, int dst_h, int dst_w, kr_dtype dst_t, const kr_normalize *norm,
+                                 void *stream)
 {
     clear_error();
     kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, KR_BORDER_REPLICATE, 0.0f,
-                               norm);
+                               norm, src_pitch);
     if (s != KR_OK)
         return s;
     ImageJob j;
     std::memset(&j, 0, sizeof j);
-    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    set_source(j, src, src_h, src_w, c, src_t, src_pitch);
+    j.dst = dst; j.dh = dst_h; j.dw = dst_w;
     const Epilogue e = make_epilogue(c, KR_BORDER_REPLICATE, 0.0f, norm);
     const hipError_t err = launch_nearest(c, src_t, dst_t, j, e, (hipStream_t)stream);
     if (err != hipSuccess)
         return fail(KR_ERR_HIP, "nearest resize launch failed: %s", hipGetErrorString(err));
     return KR_OK;
+}
+
+kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst, int dst_h,
+                            int dst_w, kr_dtype dst_t, const kr_normalize *norm, void *stream)
+{
+    return kr_resize_nearest_view(src, src_h, src_w, 0, c, src_t, dst, dst_h, dst_w, dst_t, norm, stream);
 }
 
 kr_status kr_flip(const void *src, int h, int w, int c, kr_dtype t, void *dst, int flip_x, int flip_y, void *stream)
@@ -284,12 +363,13 @@ kr_status kr_invert_homography(const double m[9], double inv[9])
     return invert_homography_impl(m, inv);
 }
 
-kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst, int dst_h,
-                              int dst_w, kr_dtype dst_t, const double m[9], int flags, kr_border border,
-                              float border_value, const kr_normalize *norm, void *stream)
+kr_status kr_warp_perspective_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
+                                   void *dst, int dst_h, int dst_w, kr_dtype dst_t, const double m[9], int flags,
+                                   kr_border border, float border_value, const kr_normalize *norm, void *stream)
 {
     clear_error();
-    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    kr_status s = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm,
+                               src_pitch);
     if (s != KR_OK)
         return s;
     if (flags & ~KR_WARP_INVERSE_MAP)
@@ -310,7 +390,8 @@ kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_d
     }
     ImageJob j;
     std::memset(&j, 0, sizeof j);
-    j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    set_source(j, src, src_h, src_w, c, src_t, src_pitch);
+    j.dst = dst; j.dh = dst_h; j.dw = dst_w;
     for (int i = 0; i < 6; i++)
         j.inv[i] = inv[i];
     for (int i = 0; i < 3; i++)
@@ -320,6 +401,14 @@ kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_d
     if (err != hipSuccess)
         return fail(KR_ERR_HIP, "perspective warp launch failed: %s", hipGetErrorString(err));
     return KR_OK;
+}
+
+kr_status kr_warp_perspective(const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst, int dst_h,
+                              int dst_w, kr_dtype dst_t, const double m[9], int flags, kr_border border,
+                              float border_value, const kr_normalize *norm, void *stream)
+{
+    return kr_warp_perspective_view(src, src_h, src_w, 0, c, src_t, dst, dst_h, dst_w, dst_t, m, flags, border,
+                                    border_value, norm, stream);
 }
 
 kr_status kr_invert_affine(const double m[6], double inv[6])

@@ -53,6 +53,8 @@ kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c
             return st;
     }
     j.src = src; j.dst = dst; j.sh = src_h; j.sw = src_w; j.dh = dst_h; j.dw = dst_w;
+    j.sp = src_w;  // contiguous source
+    j.sk = 0;
     const Epilogue e = make_epilogue(c, border, border_value, norm);
     hipStream_t s = (hipStream_t)stream;
     TileCfg best{};

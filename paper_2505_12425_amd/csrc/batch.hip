@@ -228,15 +228,15 @@ static kr_status check_items(const kr_batch_item *items, int n, int c, kr_dtype 
     for (int i = 0; i < n; i++) {
         const kr_batch_item &it = items[i];
         kr_status s = check_common(it.src, it.src_h, it.src_w, c, st, it.dst, it.dst_h, it.dst_w, dt, border, bval,
-                                   norm);
+                                   norm, it.src_pitch);
         if (s != KR_OK)
             return fail(s, "item %d: %s", i, kr_last_error());
         if (it.op != KR_OP_RESIZE && it.op != KR_OP_WARP)
             return fail(KR_ERR_INVALID_ARGUMENT, "item %d: unknown op %d", i, it.op);
         ImageJob j;
         std::memset(&j, 0, sizeof j);
-        j.src = it.src; j.dst = it.dst;
-        j.sh = it.src_h; j.sw = it.src_w; j.dh = it.dst_h; j.dw = it.dst_w;
+        set_source(j, it.src, it.src_h, it.src_w, c, st, it.src_pitch);
+        j.dst = it.dst; j.dh = it.dst_h; j.dw = it.dst_w;
         if (it.op == KR_OP_WARP) {
             if (it.flags & ~KR_WARP_INVERSE_MAP)
                 return fail(KR_ERR_INVALID_ARGUMENT, "item %d: unknown warp flags 0x%x", i, it.flags);
@@ -249,14 +249,14 @@ static kr_status check_items(const kr_batch_item *items, int n, int c, kr_dtype 
         }
     }
     // destinations must not overlap each other or any source
-    const size_t es_d = dt == KR_U8 ? 1 : 4, es_s = st == KR_U8 ? 1 : 4;
+    const size_t es_d = dt == KR_U8 ? 1 : 4;
     struct R { uintptr_t a, b; };
     std::vector<R> dsts, srcs;
     for (int i = 0; i < n; i++) {
         const uintptr_t d = reinterpret_cast<uintptr_t>(items[i].dst);
         dsts.push_back({d, d + (uintptr_t)items[i].dst_h * items[i].dst_w * c * es_d});
         const uintptr_t s0 = reinterpret_cast<uintptr_t>(items[i].src);
-        srcs.push_back({s0, s0 + (uintptr_t)items[i].src_h * items[i].src_w * c * es_s});
+        srcs.push_back({s0, s0 + source_span(items[i].src_h, items[i].src_w, c, st, items[i].src_pitch)});
     }
     std::vector<R> sd = dsts;
     std::sort(sd.begin(), sd.end(), [](const R &x, const R &y) { return x.a < y.a; });

@@ -92,8 +92,9 @@ __device__ __forceinline__ float blend_f32(float p00, float p01, float p10, floa
 
 // One tap of C channels as integers (u8 source) with the border rule.
 template <int C, typename S>
-__device__ __forceinline__ void tap_int(const S *src, int h, int w, int x, int y, const Epilogue &e, int (&p)[C])
+__device__ __forceinline__ void tap_int(const S *src, const ImageJob &j, int x, int y, const Epilogue &e, int (&p)[C])
 {
+    const int h = j.sh, w = j.sw;
     if ((unsigned)x >= (unsigned)w || (unsigned)y >= (unsigned)h) {
         if (e.border == KR_BORDER_CONSTANT) {
 #pragma unroll
@@ -104,7 +105,7 @@ __device__ __forceinline__ void tap_int(const S *src, int h, int w, int x, int y
         x = x < 0 ? 0 : (x >= w ? w - 1 : x);
         y = y < 0 ? 0 : (y >= h ? h - 1 : y);
     }
-    const S *q = src + ((size_t)y * (size_t)w + (size_t)x) * C;
+    const S *q = src + ((size_t)j.sk + (size_t)y * (size_t)j.sp + (size_t)x) * C;
 #pragma unroll
     for (int c = 0; c < C; c++)
         p[c] = (int)q[c];
@@ -112,8 +113,9 @@ __device__ __forceinline__ void tap_int(const S *src, int h, int w, int x, int y
 
 // One tap of C channels as floats with the border rule.
 template <int C, typename S>
-__device__ __forceinline__ void tap_float(const S *src, int h, int w, int x, int y, const Epilogue &e, float (&p)[C])
+__device__ __forceinline__ void tap_float(const S *src, const ImageJob &j, int x, int y, const Epilogue &e, float (&p)[C])
 {
+    const int h = j.sh, w = j.sw;
     if ((unsigned)x >= (unsigned)w || (unsigned)y >= (unsigned)h) {
         if (e.border == KR_BORDER_CONSTANT) {
 #pragma unroll
@@ -124,7 +126,7 @@ __device__ __forceinline__ void tap_float(const S *src, int h, int w, int x, int
         x = x < 0 ? 0 : (x >= w ? w - 1 : x);
         y = y < 0 ? 0 : (y >= h ? h - 1 : y);
     }
-    const S *q = src + ((size_t)y * (size_t)w + (size_t)x) * C;
+    const S *q = src + ((size_t)j.sk + (size_t)y * (size_t)j.sp + (size_t)x) * C;
 #pragma unroll
     for (int c = 0; c < C; c++)
         p[c] = (float)q[c];
@@ -169,7 +171,7 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
             for (int k = 0; k < 2; k++) {
                 const int w = wy[i] * wx[k];
                 int p[C];
-                tap_int<C>(src, j.sh, j.sw, x0 + k, y0 + i, e, p);
+                tap_int<C>(src, j, x0 + k, y0 + i, e, p);
 #pragma unroll
                 for (int c = 0; c < C; c++)
                     acc[c] += w * p[c];
@@ -180,10 +182,10 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
             dst[c] = (uint8_t)((acc[c] + (1 << 21)) >> 22);
     } else {
         float p00[C], p01[C], p10[C], p11[C];
-        tap_float<C>(src, j.sh, j.sw, x0, y0, e, p00);
-        tap_float<C>(src, j.sh, j.sw, x0 + 1, y0, e, p01);
-        tap_float<C>(src, j.sh, j.sw, x0, y0 + 1, e, p10);
-        tap_float<C>(src, j.sh, j.sw, x0 + 1, y0 + 1, e, p11);
+        tap_float<C>(src, j, x0, y0, e, p00);
+        tap_float<C>(src, j, x0 + 1, y0, e, p01);
+        tap_float<C>(src, j, x0, y0 + 1, e, p10);
+        tap_float<C>(src, j, x0 + 1, y0 + 1, e, p11);
 #pragma unroll
         for (int c = 0; c < C; c++)
             dst[c] = blend_f32(p00[c], p01[c], p10[c], p11[c], 1.0f - fx, fx, 1.0f - fy, fy, 0.0f, e.alpha[c],

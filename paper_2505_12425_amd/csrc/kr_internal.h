@@ -25,13 +25,25 @@ struct Epilogue {
 // One image as the kernels see it.  For warps, inv is the inverse map with
 // its first row and second row kept as given (not pre-scaled); perspective
 // warps add the inverse homography's third row in proj.
+//
+// Source addressing: pixel (x, y) is pixel number sk + y * sp + x counted
+// from src, which is 16-byte aligned.  A contiguous image has sp = sw and
+// sk = 0; a view into a larger buffer has its row pitch sp (in pixels) and
+// src moved back by sk < 16 pixels to the 16-byte boundary at or below its
+// first pixel.  Kernels read no pixel before number sk or after the last one
+// (the dword-aligned loads of a pixel aside, which stay inside its aligned
+// dwords).
 struct ImageJob {
     const void *src;
     void *dst;
     int sh, sw, dh, dw;
+    int sp, sk;
     double inv[6];
     double proj[3];
 };
+
+// Pixel numbers [lo, hi) that hold the source image (lo = sk).
+__host__ __device__ inline int src_end(const ImageJob &j) { return j.sk + (j.sh - 1) * j.sp + j.sw; }
 
 // Launchers (resample.hip).  All return the HIP error of the launch.
 hipError_t launch_generic(int op, int c, kr_dtype st, kr_dtype dt, const ImageJob &j,

@@ -28,6 +28,7 @@ struct NearestJob {
     const void *src;
     void *dst;
     int sh, sw, dh, dw;
+    int sp, sk;     // source row pitch and first pixel, in pixels from src
     double rx, ry;  // 1 / (2 dw), 1 / (2 dh), rounded
 };
 
@@ -46,14 +47,14 @@ __global__ __launch_bounds__(NN_TX * NN_TY) void k_nearest(NearestJob j, Epilogu
         int r;
         sx[k] = (size_t)floor_div_r((2 * min(x + k, j.dw - 1) + 1) * j.sw, 2 * j.dw, j.rx, r);
     }
-    const size_t nbytes = (size_t)j.sh * j.sw * C * (SRC_F32 ? 4 : 1);
+    const size_t nbytes = ((size_t)j.sk + (size_t)(j.sh - 1) * j.sp + j.sw) * C * (SRC_F32 ? 4 : 1);
 #pragma unroll
     for (int rr = 0; rr < S::RPT; rr++) {
         const int y = blockIdx.y * S::ROWS + threadIdx.y + rr * NN_TY;
         if (y >= j.dh)
             break;
         int r;
-        const size_t row = (size_t)floor_div_r((2 * y + 1) * j.sh, 2 * j.dh, j.ry, r) * (size_t)j.sw;
+        const size_t row = (size_t)j.sk + (size_t)floor_div_r((2 * y + 1) * j.sh, 2 * j.dh, j.ry, r) * (size_t)j.sp;
         const size_t out = ((size_t)y * j.dw + x) * C;
         if constexpr (!DST_F32) {
             uint32_t P[4];
@@ -110,7 +111,7 @@ hipError_t launch_c(const NearestJob &j, kr_dtype st, kr_dtype dt, const Epilogu
 
 hipError_t launch_nearest(int c, kr_dtype st, kr_dtype dt, const ImageJob &ij, const Epilogue &e, hipStream_t s)
 {
-    NearestJob j{ij.src, ij.dst, ij.sh, ij.sw, ij.dh, ij.dw, 1.0 / (2.0 * ij.dw), 1.0 / (2.0 * ij.dh)};
+    NearestJob j{ij.src, ij.dst, ij.sh, ij.sw, ij.dh, ij.dw, ij.sp, ij.sk, 1.0 / (2.0 * ij.dw), 1.0 / (2.0 * ij.dh)};
     switch (c) {
     case 1: return launch_c<1>(j, st, dt, e, s);
     case 2: return launch_c<2>(j, st, dt, e, s);

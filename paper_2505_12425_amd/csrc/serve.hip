@@ -46,6 +46,8 @@ struct HipExec {
             j.src = a.req.src;
             j.dst = arena_base + a.dst_off;
             j.sh = a.req.sh; j.sw = a.req.sw; j.dh = a.req.dh; j.dw = a.req.dw;
+            j.sp = a.req.sw;  // contiguous source
+            j.sk = 0;
             for (int i = 0; i < 6; i++)
                 j.inv[i] = a.req.m[i];
             imgs[a.req.op == OP_WARP ? 1 : 0].push_back(j);

@@ -614,7 +614,7 @@ __device__ __forceinline__ bool group_of(const TiledJob &t, const Plan &p, const
     // different LDS banks
     const int gi = udiv_small(k, p.nslots);
     const int s = k - gi * p.nslots;
-    const int rowbase = slot_row<OP>(t, p, s) * t.j.sw;
+    const int rowbase = t.j.sk + slot_row<OP>(t, p, s) * t.j.sp;
     const int g = ((rowbase + p.cx0) >> 4) + gi;
     if (g > ((rowbase + p.cx1) >> 4))
         return false;
@@ -658,12 +658,14 @@ __device__ __forceinline__ void write_group(uint32_t *d, const GroupRegs<C> &r)
     }
 }
 
-// The image's last group may end past the buffer: read it pixel by pixel.
+// A group that reaches before the image's first pixel or past its last one
+// (views into larger buffers; the last group of any image): its pixels
+// inside [lo, hi) one by one.
 template <int C>
-__device__ __noinline__ void write_tail_group(uint32_t *d, const uint8_t *src, int p0, int hw)
+__device__ __noinline__ void write_tail_group(uint32_t *d, const uint8_t *src, int p0, int lo, int hi)
 {
 #pragma unroll 1
-    for (int i = 0; i < 16 && p0 + i < hw; i++)
+    for (int i = p0 < lo ? lo - p0 : 0; i < 16 && p0 + i < hi; i++)
         d[i] = load_px_bytes<C>(src, (size_t)(p0 + i));
 }
 
@@ -672,7 +674,7 @@ template <int OP, int C, int MAXIT>
 __device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const TileGeom &G, Prefetch<C, MAXIT> &pf)
 {
     const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
-    const int hw = t.j.sh * t.j.sw;
+    const int lo = t.j.sk, hi = src_end(t.j);
     const int total = p.nslots * p.ng;
 #pragma unroll
     for (int it = 0; it < MAXIT; it++) {
@@ -682,7 +684,7 @@ __device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const
         if (k < total && group_of<OP>(t, p, G, k, dst, p0)) {
             pf.dst[it] = dst;
             pf.p0[it] = p0;
-            if (p0 + 16 <= hw)
+            if (p0 >= lo && p0 + 16 <= hi)
                 load_group<C>(src, p0, pf.g[it]);
         }
     }
@@ -695,14 +697,14 @@ __device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const T
                                        const Prefetch<C, MAXIT> &pf, uint32_t *lds)
 {
     const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
-    const int hw = t.j.sh * t.j.sw;
+    const int lo = t.j.sk, hi = src_end(t.j);
 #pragma unroll
     for (int it = 0; it < MAXIT; it++) {
         if (pf.dst[it] >= 0) {
-            if (pf.p0[it] + 16 <= hw)
+            if (pf.p0[it] >= lo && pf.p0[it] + 16 <= hi)
                 write_group<C>(lds + pf.dst[it], pf.g[it]);
             else
-                write_tail_group<C>(lds + pf.dst[it], src, pf.p0[it], hw);
+                write_tail_group<C>(lds + pf.dst[it], src, pf.p0[it], lo, hi);
         }
     }
     const int total = p.nslots * p.ng;
@@ -710,12 +712,12 @@ __device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const T
         int dst, p0;
         if (!group_of<OP>(t, p, G, k, dst, p0))
             continue;
-        if (p0 + 16 <= hw) {
+        if (p0 >= lo && p0 + 16 <= hi) {
             GroupRegs<C> r;
             load_group<C>(src, p0, r);
             write_group<C>(lds + dst, r);
         } else {
-            write_tail_group<C>(lds + dst, src, p0, hw);
+            write_tail_group<C>(lds + dst, src, p0, lo, hi);
         }
     }
 }
@@ -742,7 +744,8 @@ __device__ __forceinline__ void fill_edge_columns(const TiledJob &t, const Plan 
         const int jj = k - s * per;
         const int col = jj < nl ? jj : p.bw - nr + (jj - nl);
         const int xc = clampi(p.bx0 + col, 0, W - 1);
-        lds[s * G.pitch + KT_MARGIN + col] = load_px_bytes<C>(src, (size_t)slot_row<OP>(t, p, s) * W + xc);
+        lds[s * G.pitch + KT_MARGIN + col] =
+            load_px_bytes<C>(src, (size_t)t.j.sk + (size_t)slot_row<OP>(t, p, s) * t.j.sp + xc);
     }
 }
 
@@ -1045,22 +1048,25 @@ __device__ __forceinline__ void load_tap_pair(const uint8_t *__restrict__ src, s
 // tap lies outside the image; the taps then hold the clamped (edge) pixels,
 // which is the REPLICATE rule, and a CONSTANT border masks their weights.
 template <int C>
-__device__ __forceinline__ bool load_taps(const uint8_t *__restrict__ src, int W, int H, int x0, int y0, uint32_t &t00,
-                                          uint32_t &t01, uint32_t &t10, uint32_t &t11)
+__device__ __forceinline__ bool load_taps(const ImageJob &j, int x0, int y0, uint32_t &t00, uint32_t &t01,
+                                          uint32_t &t10, uint32_t &t11)
 {
-    const size_t nbytes = (size_t)W * H * C;
+    const uint8_t *src = static_cast<const uint8_t *>(j.src);
+    const int W = j.sw, H = j.sh;
+    const size_t sp = (size_t)j.sp, sk = (size_t)j.sk;
+    const size_t nbytes = (size_t)src_end(j) * C;
     if ((unsigned)x0 < (unsigned)(W - 1) && (unsigned)y0 < (unsigned)(H - 1)) {
-        const size_t lin = (size_t)y0 * W + x0;
+        const size_t lin = sk + (size_t)y0 * sp + x0;
         load_tap_pair<C>(src, nbytes, lin, t00, t01);
-        load_tap_pair<C>(src, nbytes, lin + W, t10, t11);
+        load_tap_pair<C>(src, nbytes, lin + sp, t10, t11);
         return true;
     }
     const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
     const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
-    t00 = load_px_bytes<C>(src, (size_t)ya * W + xa);
-    t01 = load_px_bytes<C>(src, (size_t)ya * W + xb);
-    t10 = load_px_bytes<C>(src, (size_t)yb * W + xa);
-    t11 = load_px_bytes<C>(src, (size_t)yb * W + xb);
+    t00 = load_px_bytes<C>(src, sk + (size_t)ya * sp + xa);
+    t01 = load_px_bytes<C>(src, sk + (size_t)ya * sp + xb);
+    t10 = load_px_bytes<C>(src, sk + (size_t)yb * sp + xa);
+    t11 = load_px_bytes<C>(src, sk + (size_t)yb * sp + xb);
     return false;
 }
 
@@ -1070,7 +1076,7 @@ __device__ __forceinline__ uint32_t gather_px_u8(const ImageJob &j, const Epilog
                                                  uint32_t wy1)
 {
     uint32_t t00, t01, t10, t11;
-    const bool in = load_taps<C>(static_cast<const uint8_t *>(j.src), j.sw, j.sh, x0, y0, t00, t01, t10, t11);
+    const bool in = load_taps<C>(j, x0, y0, t00, t01, t10, t11);
     uint32_t wx0 = 2048u - wx1, wy0 = 2048u - wy1, corr = 0;
     if (!in && e.border == KR_BORDER_CONSTANT)
         corr = mask_weights(x0, y0, j.sw, j.sh, wx0, wx1, wy0, wy1, (uint32_t)e.bval_i);
@@ -1087,7 +1093,7 @@ __device__ __forceinline__ void gather_px_f32(const ImageJob &j, const Epilogue 
                                               float (&o)[C])
 {
     uint32_t t00, t01, t10, t11;
-    const bool in = load_taps<C>(static_cast<const uint8_t *>(j.src), j.sw, j.sh, x0, y0, t00, t01, t10, t11);
+    const bool in = load_taps<C>(j, x0, y0, t00, t01, t10, t11);
     float wx0 = 1.0f - fx, wx1 = fx, wy0 = 1.0f - fy, wy1 = fy, extra = 0.0f;
     if (!in && e.border == KR_BORDER_CONSTANT) {
         const int W = j.sw, H = j.sh;

@@ -48,7 +48,8 @@ class Normalize(ctypes.Structure):
 class BatchItem(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("src", ctypes.c_void_p), ("src_h", ctypes.c_int),
                 ("src_w", ctypes.c_int), ("dst", ctypes.c_void_p), ("dst_h", ctypes.c_int),
-                ("dst_w", ctypes.c_int), ("m", ctypes.c_double * 6), ("flags", ctypes.c_int)]
+                ("dst_w", ctypes.c_int), ("m", ctypes.c_double * 6), ("flags", ctypes.c_int),
+                ("src_pitch", ctypes.c_size_t)]
 
 
 _lib = None
@@ -73,6 +74,15 @@ def lib():
     L.kr_resize_nearest.restype = i
     L.kr_warp_perspective.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
     L.kr_warp_perspective.restype = i
+    sz_ = ctypes.c_size_t
+    L.kr_resize_bilinear_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, i, i, f, npp, vp]
+    L.kr_resize_bilinear_view.restype = i
+    L.kr_warp_affine_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
+    L.kr_warp_affine_view.restype = i
+    L.kr_warp_perspective_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
+    L.kr_warp_perspective_view.restype = i
+    L.kr_resize_nearest_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, i, npp, vp]
+    L.kr_resize_nearest_view.restype = i
     L.kr_invert_homography.argtypes = [dp, dp]
     L.kr_invert_homography.restype = i
     L.kr_flip.argtypes = [vp, i, i, i, i, vp, i, i, vp]
@@ -170,6 +180,34 @@ def _image(t):
     return t.data_ptr(), int(h), int(w), int(c), dt
 
 
+def _dtype(t) -> int:
+    import torch
+    if t.dtype == torch.uint8:
+        return U8
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _source(t):
+    """(pointer, H, W, pitch bytes, C, kr_dtype) of an HWC (or HW) device tensor
+    that may be a view: pixels and channels packed (channel stride 1, pixel
+    stride C), rows any whole number of pixels apart.  pitch is 0 for a
+    contiguous tensor that starts on a 16-byte boundary (the plain entry
+    points); anything else goes through the view entry points."""
+    if t.is_contiguous() and t.data_ptr() % 16 == 0:
+        ptr, h, w, c, dt = _image(t)
+        return ptr, h, w, 0, c, dt
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if t.dim() not in (2, 3):
+        raise ValueError("tensor must be HxW or HxWxC")
+    c = 1 if t.dim() == 2 else int(t.shape[2])
+    if t.stride(-1) != 1 or (t.dim() == 3 and t.stride(1) != c):
+        raise ValueError("source view must have packed pixels (channel stride 1, pixel stride C)")
+    return (t.data_ptr(), int(t.shape[0]), int(t.shape[1]), int(t.stride(0)) * t.element_size(), c, _dtype(t))
+
+
 def _stream(stream):
     if stream is not None:
         return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
@@ -180,21 +218,28 @@ def _stream(stream):
 def resize(src, dst, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
            stream=None) -> None:
     """kr_resize_bilinear on torch tensors: src HWC u8/f32 -> dst HWC (its size is the target)."""
-    sp, sh, sw, c, st = _image(src)
+    sp, sh, sw, pitch, c, st = _source(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if dc != c:
         raise ValueError("src and dst channel counts differ")
-    check(lib().kr_resize_bilinear(sp, sh, sw, c, st, dp_, dh, dw, dt, border, float(border_value),
-                                   _normalize(mean, std, c), _stream(stream)))
+    args = (dp_, dh, dw, dt, border, float(border_value), _normalize(mean, std, c), _stream(stream))
+    if pitch:
+        check(lib().kr_resize_bilinear_view(sp, sh, sw, pitch, c, st, *args))
+    else:
+        check(lib().kr_resize_bilinear(sp, sh, sw, c, st, *args))
 
 
 def resize_nearest(src, dst, mean=None, std=None, stream=None) -> None:
     """kr_resize_nearest on torch tensors: src HWC -> dst HWC (its size is the target)."""
-    sp, sh, sw, c, st = _image(src)
+    sp, sh, sw, pitch, c, st = _source(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if dc != c:
         raise ValueError("src and dst channel counts differ")
-    check(lib().kr_resize_nearest(sp, sh, sw, c, st, dp_, dh, dw, dt, _normalize(mean, std, c), _stream(stream)))
+    args = (dp_, dh, dw, dt, _normalize(mean, std, c), _stream(stream))
+    if pitch:
+        check(lib().kr_resize_nearest_view(sp, sh, sw, pitch, c, st, *args))
+    else:
+        check(lib().kr_resize_nearest(sp, sh, sw, c, st, *args))
 
 
 def flip(src, dst, flip_x: bool = True, flip_y: bool = False, stream=None) -> None:
@@ -219,13 +264,16 @@ def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, bord
                 mean=None, std=None, stream=None) -> None:
     """kr_warp_affine on torch tensors; m is the row-major 2x3 map (source->destination
     unless inverse)."""
-    sp, sh, sw, c, st = _image(src)
+    sp, sh, sw, pitch, c, st = _source(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if dc != c:
         raise ValueError("src and dst channel counts differ")
-    check(lib().kr_warp_affine(sp, sh, sw, c, st, dp_, dh, dw, dt, _m6(m),
-                               WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
-                               _normalize(mean, std, c), _stream(stream)))
+    args = (dp_, dh, dw, dt, _m6(m), WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
+            _normalize(mean, std, c), _stream(stream))
+    if pitch:
+        check(lib().kr_warp_affine_view(sp, sh, sw, pitch, c, st, *args))
+    else:
+        check(lib().kr_warp_affine(sp, sh, sw, c, st, *args))
 
 
 def _m9(m):
@@ -239,13 +287,16 @@ def warp_perspective(src, dst, m, inverse: bool = False, border: int = CONSTANT,
                      mean=None, std=None, stream=None) -> None:
     """kr_warp_perspective on torch tensors; m is the row-major 3x3 homography
     (source->destination unless inverse)."""
-    sp, sh, sw, c, st = _image(src)
+    sp, sh, sw, pitch, c, st = _source(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if dc != c:
         raise ValueError("src and dst channel counts differ")
-    check(lib().kr_warp_perspective(sp, sh, sw, c, st, dp_, dh, dw, dt, _m9(m),
-                                    WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
-                                    _normalize(mean, std, c), _stream(stream)))
+    args = (dp_, dh, dw, dt, _m9(m), WARP_INVERSE_MAP if inverse else 0, border, float(border_value),
+            _normalize(mean, std, c), _stream(stream))
+    if pitch:
+        check(lib().kr_warp_perspective_view(sp, sh, sw, pitch, c, st, *args))
+    else:
+        check(lib().kr_warp_perspective(sp, sh, sw, c, st, *args))
 
 
 def invert_homography(m):
@@ -279,21 +330,21 @@ def _image_chw(t):
 
 def _batch_items(specs, layout: int = LAYOUT_HWC):
     """ctypes array of BatchItem from specs: dicts with keys op ("resize" or
-    "warp"), src, dst (tensors; dst CxHxW for the planar layout), and for
-    warps m (2x3) and optional inverse."""
+    "warp"), src, dst (tensors; src may be a view with packed pixels, dst CxHxW
+    for the planar layout), and for warps m (2x3) and optional inverse."""
     n = len(specs)
     arr = (BatchItem * max(n, 1))()
     c = st = dt = None
     for i, sp in enumerate(specs):
         sp_ = dict(sp)
-        sptr, sh, sw, sc, s_t = _image(sp_["src"])
+        sptr, sh, sw, pitch, sc, s_t = _source(sp_["src"])
         dptr, dh, dw, dc, d_t = _image_chw(sp_["dst"]) if layout == LAYOUT_CHW else _image(sp_["dst"])
         if sc != dc or (c is not None and (sc != c or s_t != st or d_t != dt)):
             raise ValueError("batch items must share channel count and dtypes")
         c, st, dt = sc, s_t, d_t
         it = arr[i]
         it.op = OP_WARP if sp_.get("op", "resize") == "warp" else OP_RESIZE
-        it.src, it.src_h, it.src_w = sptr, sh, sw
+        it.src, it.src_h, it.src_w, it.src_pitch = sptr, sh, sw, pitch
         it.dst, it.dst_h, it.dst_w = dptr, dh, dw
         if it.op == OP_WARP:
             vals = [float(v) for v in (sp_["m"].reshape(-1).tolist() if hasattr(sp_["m"], "reshape") else sp_["m"])]

@@ -323,3 +323,72 @@ def test_perspective_validation():
     nan = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, math.nan)
     assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, nan, 1, 0, 0.0, None, None) == kr.ERR_SINGULAR_MATRIX
     assert f(A, 480, 640, 3, kr.U8, B, 480, 640, kr.U8, m, 0, 0, 300.0, None, None) == kr.ERR_INVALID_ARGUMENT
+
+
+# ---------------------------------------------------------------- source views
+def view_call(fn, pitch, src=A + 3 * 7, c=3, st=kr.U8, sh=100, sw=200, dst=B, **kw):
+    """Call one of the *_view entry points with defaults that pass validation."""
+    L = kr.lib()
+    n = kw.pop("norm", None)
+    dt = st  # (U8, U8) or (F32, F32)
+    if fn == "resize":
+        return L.kr_resize_bilinear_view(src, sh, sw, pitch, c, st, dst, 50, 100, dt, kr.REPLICATE, 0.0, n, None)
+    if fn == "nearest":
+        return L.kr_resize_nearest_view(src, sh, sw, pitch, c, st, dst, 50, 100, dt, n, None)
+    if fn == "warp":
+        mm = (ctypes.c_double * 6)(1, 0, 0, 0, 1, 0)
+        return L.kr_warp_affine_view(src, sh, sw, pitch, c, st, dst, 50, 100, dt, mm, 0, kr.CONSTANT, 0.0, n, None)
+    mm = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    return L.kr_warp_perspective_view(src, sh, sw, pitch, c, st, dst, 50, 100, dt, mm, 0, kr.CONSTANT, 0.0, n,
+                                      None)
+
+
+@pytest.mark.parametrize("fn", ["resize", "nearest", "warp", "persp"])
+def test_view_validation(fn):
+    # validation fails before anything touches the (fake) pointers; a valid
+    # call on a CPU-only host would reach the HIP launch, so only rejections
+    # are exercised here
+    inval = kr.ERR_INVALID_ARGUMENT
+    assert view_call(fn, 599) == inval                    # pitch below one row (600 bytes)
+    assert view_call(fn, 601) == inval                    # pitch not a whole number of pixels
+    assert view_call(fn, 3 * 1000, src=0) == inval        # NULL
+    assert view_call(fn, 3 * 1000, sh=0) == inval         # empty
+    # RGBA u8: the first pixel must be a whole number of 4-byte pixels past a
+    # 16-byte boundary
+    assert view_call(fn, 4 * 1000, src=A + 2, c=4) == inval
+    # f32 RGB: 12-byte pixels; an address 2 bytes off the element grid fails
+    assert view_call(fn, 12 * 1000, src=A + 2, st=kr.F32) == inval
+    # a view spanning more than 2^31 pixels
+    assert view_call(fn, 3 * 80000, sh=30000, sw=30000) == inval
+    # the view's span reaches the destination
+    assert view_call(fn, 3 * 1000, dst=A + 16 * 18000) == inval  # inside rows 95..96 of the span
+    assert "overlap" in kr.last_error()
+
+
+def test_view_shift_rule():
+    """Which view starts are accepted follows the 16-byte-boundary rule for
+    each pixel size (checked through the error the pitch test leaves)."""
+    L = kr.lib()
+
+    def ok(addr, c, st):
+        # an invalid pitch (below one row) fails after the start test: the
+        # message says which test failed
+        s = L.kr_resize_bilinear_view(addr, 10, 10, 1, c, st, B, 5, 5, kr.U8 if st == kr.U8 else kr.F32,
+                                      kr.REPLICATE, 0.0, None, None)
+        assert s == kr.ERR_INVALID_ARGUMENT
+        return "16-byte" not in kr.last_error()
+
+    for off in range(16):
+        assert ok(A + off, 3, kr.U8)                # 3-byte pixels reach every byte address
+        assert ok(A + off, 1, kr.U8)
+        assert ok(A + off, 2, kr.U8) == (off % 2 == 0)
+        assert ok(A + off, 4, kr.U8) == (off % 4 == 0)
+        assert ok(A + off, 3, kr.F32) == (off % 4 == 0)
+        assert ok(A + off, 4, kr.F32) == (off == 0)
+
+
+def test_batch_item_layout_matches_header():
+    # the ctypes mirror of kr_batch_item ends with the source pitch
+    names = [f[0] for f in kr.BatchItem._fields_]
+    assert names[-1] == "src_pitch"
+    assert ctypes.sizeof(kr.BatchItem) % 8 == 0

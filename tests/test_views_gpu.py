@@ -1,0 +1,181 @@
+"""GPU parity of source views: the *_view entry points (and batch items with a
+source pitch) read a crop of a larger buffer in place.  The expected output is
+the oracle's on a contiguous copy of the crop (u8 bit-exact, f32 within 1e-3),
+and the view call must also equal the plain call on that copy bit for bit.
+
+Crops start at pixel offsets that leave the first pixel off a 16-byte
+boundary (so the staging loads start before it and the kernels' head checks
+matter), touch the parent's first byte, and end on the parent's last byte
+(tail checks); parents are allocated at exactly their size."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_12425_amd import workloads as wl
+from tests.gpu_util import assert_f32_close, assert_u8_equal, empty, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_12425_amd import kr  # noqa: E402
+
+TH = 16
+CONST, REPL = 0, 1
+
+# (parent h, w), crop (y, x, h, w): interior with an odd x offset, the parent's
+# first pixel, the parent's bottom-right corner (last byte), a one-column and
+# a one-row crop, and a crop as wide as the parent
+CROPS = [
+    ((150, 211), (17, 13, 97, 150)),
+    ((150, 211), (0, 0, 90, 130)),
+    ((150, 211), (61, 78, 89, 133)),
+    ((120, 100), (5, 37, 60, 1)),
+    ((120, 100), (119, 3, 1, 90)),
+    ((120, 100), (9, 0, 70, 100)),
+]
+
+
+def parent_and_view(ph, pw, c, crop, f32=False, seed=0):
+    img = wl.uniform_f32(ph, pw, c, seed) if f32 else wl.uniform_u8(ph, pw, c, seed)
+    par = torch.from_numpy(img).cuda()  # allocated at exactly the parent's size
+    y, x, h, w = crop
+    view = par[y:y + h, x:x + w]
+    return par, view, np.ascontiguousarray(img[y:y + h, x:x + w])
+
+
+def run(op, src, dh, dw, out, c, **kw):
+    d = empty(dh, dw, c, out)
+    if op == "resize":
+        kr.resize(src, d, border=kw.get("border", REPL))
+    elif op == "nearest":
+        kr.resize_nearest(src, d)
+    elif op == "warp":
+        kr.warp_affine(src, d, kw["m"], border=kw.get("border", CONST), border_value=kw.get("bval", 0.0))
+    else:
+        kr.warp_perspective(src, d, kw["m"], border=kw.get("border", CONST), border_value=kw.get("bval", 0.0))
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+def expect(op, crop, dh, dw, out, **kw):
+    o = "u8" if out == "u8" else "f64"
+    if op == "resize":
+        return oracle.resize(crop, dh, dw, o, kw.get("border", REPL), threads=TH)
+    if op == "nearest":
+        return oracle.resize_nearest(crop, dh, dw, o, threads=TH)
+    if op == "warp":
+        return oracle.warp(crop, kw["m"], dh, dw, o, False, kw.get("border", CONST), kw.get("bval", 0.0), threads=TH)
+    return oracle.warp_perspective(crop, kw["m"], dh, dw, o, False, kw.get("border", CONST), kw.get("bval", 0.0),
+                                   threads=TH)
+
+
+def op_args(op, h, w, seed):
+    rng = np.random.default_rng(seed)
+    if op == "warp":
+        return {"m": wl.affine_compose(h, w, float(rng.uniform(-40, 40)), float(rng.uniform(0.7, 1.3)),
+                                       float(rng.uniform(-0.2, 0.2)), float(rng.uniform(-5, 5)),
+                                       float(rng.uniform(-5, 5)))}
+    if op == "persp":
+        if h < 2 or w < 2:  # no four-corner fit for a single row or column
+            return {"m": np.array([[1.0, 0.05, 0.3], [-0.02, 1.0, -0.2], [1e-3, 2e-3, 1.0]])}
+        return {"m": wl.random_homography(h, w, rng, 0.2)}
+    return {}
+
+
+def out_size(op, h, w):
+    if op in ("resize", "nearest"):
+        return max(1, (h * 2) // 3), max(1, (w * 5) // 4)
+    return h + 3, w - (1 if w > 1 else 0)
+
+
+@pytest.mark.parametrize("op", ["resize", "nearest", "warp", "persp"])
+@pytest.mark.parametrize("c", [3, 4, 1])
+def test_view_u8_source(op, c):
+    for k, ((ph, pw), crop) in enumerate(CROPS):
+        par, view, host = parent_and_view(ph, pw, c, crop, seed=k)
+        h, w = host.shape[:2]
+        dh, dw = out_size(op, h, w)
+        kw = op_args(op, h, w, k)
+        for border in ([CONST, REPL] if op in ("warp", "persp") else [REPL]):
+            kw2 = dict(kw, border=border, bval=7.0)
+            what = f"{op} c={c} crop {crop} of {ph}x{pw} border {border}"
+            say(what)
+            for out in ("u8", "f32"):
+                got = run(op, view, dh, dw, out, c, **kw2)
+                plain = run(op, torch.from_numpy(host).cuda(), dh, dw, out, c, **kw2)
+                assert np.array_equal(got.view(np.uint8), plain.view(np.uint8)), what + " view != plain " + out
+                exp = expect(op, host, dh, dw, out, **kw2)
+                if out == "u8":
+                    assert_u8_equal(got, exp, what)
+                else:
+                    assert_f32_close(got, exp, what)
+
+
+@pytest.mark.parametrize("op", ["resize", "warp", "persp", "nearest"])
+def test_view_f32_source(op):
+    for k, ((ph, pw), crop) in enumerate(CROPS[:3]):
+        par, view, host = parent_and_view(ph, pw, 3, crop, f32=True, seed=k)
+        h, w = host.shape[:2]
+        dh, dw = out_size(op, h, w)
+        kw = op_args(op, h, w, k)
+        what = f"f32 {op} crop {crop}"
+        say(what)
+        got = run(op, view, dh, dw, "f32", 3, **kw)
+        assert_f32_close(got, expect(op, host, dh, dw, "f32", **kw), what)
+
+
+def test_view_4k_crop_tiled_path():
+    """A 1920x1080 crop at an odd offset of a 4K frame: the LDS-tiled kernels'
+    staging over many tiles and a ragged edge, resize and warp, u8 and f32."""
+    par, view, host = parent_and_view(2160, 3840, 3, (333, 1001, 1080, 1920), seed=5)
+    m = wl.random_affine_4k(1080, 1920, 1)
+    for op, dh, dw, kw in (("resize", 517, 961, {}), ("warp", 1080, 1920, {"m": m})):
+        for out in ("u8", "f32"):
+            what = f"4K crop {op} {out}"
+            say(what)
+            got = run(op, view, dh, dw, out, 3, **kw)
+            plain = run(op, torch.from_numpy(host).cuda(), dh, dw, out, 3, **kw)
+            assert np.array_equal(got.view(np.uint8), plain.view(np.uint8)), what
+
+
+def test_batch_items_with_views():
+    """Batch items whose sources are crops (resizes and warps, u8 -> u8 and
+    u8 -> f32 normalised) equal the single-image calls on contiguous copies."""
+    rng = np.random.default_rng(3)
+    par = torch.from_numpy(wl.uniform_u8(700, 900, 3, 11)).cuda()
+    mean, std = (0.485, 0.456, 0.406), (0.229, 0.224, 0.225)
+    for out in ("u8", "f32"):
+        specs, refs = [], []
+        for i in range(12):
+            h, w = int(rng.integers(20, 300)), int(rng.integers(20, 400))
+            y, x = int(rng.integers(0, 700 - h + 1)), int(rng.integers(0, 900 - w + 1))
+            view = par[y:y + h, x:x + w]
+            host = torch.from_numpy(np.ascontiguousarray(par[y:y + h, x:x + w].cpu().numpy())).cuda()
+            dst = empty(int(rng.integers(16, 200)), int(rng.integers(16, 200)), 3, out)
+            ref = torch.empty_like(dst)
+            if i % 3 == 2:
+                m = wl.affine_compose(h, w, float(rng.uniform(-30, 30)), 1.0, 0.0, 2.0, -1.0)
+                specs.append({"op": "warp", "src": view, "dst": dst, "m": m})
+                if out == "u8":
+                    kr.warp_affine(host, ref, m, border=REPL)
+                else:
+                    kr.warp_affine(host, ref, m, border=REPL, mean=mean, std=std)
+            else:
+                specs.append({"op": "resize", "src": view, "dst": dst})
+                if out == "u8":
+                    kr.resize(host, ref, border=REPL)
+                else:
+                    kr.resize(host, ref, border=REPL, mean=mean, std=std)
+            refs.append(ref)
+        say(f"batch of views, {out}")
+        if out == "u8":
+            kr.resize_batch(specs, border=REPL)
+        else:
+            kr.resize_batch(specs, border=REPL, mean=mean, std=std)
+        torch.cuda.synchronize()
+        for i, (sp, ref) in enumerate(zip(specs, refs)):
+            assert torch.equal(sp["dst"].view(torch.uint8), ref.view(torch.uint8)), f"batch item {i} {out}"
