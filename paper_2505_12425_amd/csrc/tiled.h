@@ -445,6 +445,8 @@ struct Plan {
     int cx0, cx1, ng;        // in-image box columns; 16-pixel groups per slot (upper bound)
     bool inside;             // every tap of the tile lies inside the image
     bool direct;             // box exceeds the LDS budget: per-pixel evaluation
+    bool blank;              // warps, CONSTANT border: every tap lies outside the image,
+                             // so every output is the border value (nothing staged)
 };
 
 // u8 coordinate of one axis: the 2048-scaled binary64 coordinate X gives
@@ -477,7 +479,7 @@ __device__ __forceinline__ double persp_coord(double num, double w, int n)
 }
 
 template <int OP, int TW, int TH, bool F32>
-__device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const TileGeom &G)
+__device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const TileGeom &G, bool constant_border)
 {
     const ImageJob &j = t.j;
     const int H = j.sh, W = j.sw;
@@ -573,9 +575,18 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
     p.bx0 = x0min;
     p.bw = x0max + 2 - x0min;
     p.direct = !persp_ok || p.bw + 2 * KT_MARGIN > G.pitch || p.nslots > G.rows;
+    // The bounds hold every pixel's top-left tap (x0, y0); its taps are x0,
+    // x0 + 1 and y0, y0 + 1.  If all of them fall left of, right of, above or
+    // below the image, every tap reads the border constant, whose weights sum
+    // to one: the u8 result is the border value exactly, the f32 one is
+    // 0 + b before the epilogue, as on the interpolating path.
+    p.blank = OP != OP_RESIZE && constant_border && persp_ok &&
+              (x0max + 1 < 0 || x0min > W - 1 || y0max + 1 < 0 || y0min > H - 1);
+    if (p.blank)
+        p.direct = false;
     p.cx0 = max(p.bx0, 0);
     p.cx1 = min(p.bx0 + p.bw - 1, W - 1);
-    p.ng = (p.direct || p.cx0 > p.cx1) ? 0 : ((p.cx1 - p.cx0) >> 4) + 2;
+    p.ng = (p.direct || p.blank || p.cx0 > p.cx1) ? 0 : ((p.cx1 - p.cx0) >> 4) + 2;
     return p;
 }
 
@@ -1202,6 +1213,43 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
     }
 }
 
+// A blank tile (see Plan::blank): every output pixel is the border value,
+// u8: b in each channel; f32: fma(0 + b, alpha_c, beta_c), the bits the
+// interpolating path produces when every weight is masked.
+template <int C, bool F32, class L>
+__device__ __forceinline__ void fill_blank(const TiledJob &t, const Plan &p, const Epilogue &e)
+{
+    constexpr int PX = L::PX, CPT = L::CPT;
+    const ImageJob &j = t.j;
+    const bool aligned = layout_aligned<C, F32, L>(j.dw);
+    const uint32_t sel = quad_selector(lane_id() & 3);
+    const int x_end = p.ox1 + 1;
+    uint32_t P[PX];
+    float o[PX][C];
+    const uint32_t b = (uint32_t)e.bval_i;
+    const uint32_t pix = C == 1 ? b : (C == 2 ? b * 0x101u : (C == 3 ? b * 0x10101u : b * 0x1010101u));
+#pragma unroll
+    for (int k = 0; k < PX; k++) {
+        P[k] = pix;
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            o[k][c] = __builtin_fmaf(0.0f + e.bval_f, e.alpha[c], e.beta[c]);
+    }
+    for (int r = 0; r < L::RPT; r++) {
+        const int y = p.oy0 + L::row0() + r * L::ROWS;
+        if (y > p.oy1)
+            break;
+#pragma unroll
+        for (int c = 0; c < CPT; c++) {
+            const int xr = p.ox0 + c * L::SEG + L::col0();
+            if constexpr (!F32)
+                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
+            else
+                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ tile pipeline
 // Stage -> (edge fill) -> issue the next tile's loads -> compute this tile.
 // The next tile's global loads stay in flight in registers while this tile is
@@ -1216,7 +1264,8 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
     int tile;
     if (!next_job(t, tile))
         return;
-    Plan p = make_plan<OP, TW, TH, F32>(t, tile, G);
+    const bool cb = e.border == KR_BORDER_CONSTANT;
+    Plan p = make_plan<OP, TW, TH, F32>(t, tile, G, cb);
     if constexpr (!PIPE) {
         if (!p.direct) {
             Prefetch<C, MAXIT> pf;
@@ -1230,7 +1279,9 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
             fill_edge_columns<OP, C>(t, p, G, lds);
             __syncthreads();
         }
-        if (p.direct)
+        if (p.blank)
+            fill_blank<C, F32, L>(t, p, e);
+        else if (p.direct)
             compute_gather<OP, C, F32, L>(t, p, G, e, lds);
         else if constexpr (OP == OP_RESIZE)
             compute_resize<C, F32, L>(t, p, G, e, lds);
@@ -1255,10 +1306,12 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         const bool more = next_job(nt, ntile);
         Plan np;
         if (more) {
-            np = make_plan<OP, TW, TH, F32>(nt, ntile, G);
+            np = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
             prefetch<OP, C, MAXIT>(nt, np, G, pf);
         }
-        if (p.direct)
+        if (p.blank)
+            fill_blank<C, F32, L>(t, p, e);
+        else if (p.direct)
             compute_gather<OP, C, F32, L>(t, p, G, e, lds);
         else if constexpr (OP == OP_RESIZE)
             compute_resize<C, F32, L>(t, p, G, e, lds);

@@ -163,6 +163,20 @@ def test_all_border_warp():
     assert (got == 42).all()
 
 
+def test_blank_tiles_match_oracle():
+    """Zoomed-out and shifted warps whose output is mostly border: tiles with
+    every tap outside the source take the constant fill, their neighbours
+    interpolate; both must equal the oracle (u8 bit-exact, f32 and
+    normalised f32 within tolerance), with a non-zero border value, for RGB
+    and RGBA."""
+    for c in (3, 4):
+        img = wl.uniform_u8(300, 410, c, seed=65 + c)
+        for k, (th, sc, tx, ty) in enumerate([(17.0, 0.3, 0.0, 0.0), (-38.0, 0.45, 260.0, -90.0),
+                                              (0.0, 1.0, 700.0, 0.0), (90.0, 0.2, -30.0, 40.0)]):
+            m = wl.affine_compose(300, 410, th, sc, 0.0, tx, ty)
+            check_warp(img, m, 333, 517, CONST, 37, what=f"blank tiles c={c} case {k}")
+
+
 def test_huge_coefficients():
     img = wl.uniform_u8(64, 64, 3, seed=63)
     inv = [1.0e14 + 1.0 / 64, 0.0, -5.0e14 + 3.3, 0.0, 1.0, 0.25]

@@ -88,3 +88,12 @@ def test_affine_special_case_equals_affine_warp():
         kr.warp_perspective(s, p, inv6 + [0.0, 0.0, 1.0], inverse=True, border=REPL)
         torch.cuda.synchronize()
         assert np.array_equal(a.cpu().numpy(), p.cpu().numpy()), out
+
+
+def test_mostly_border_output():
+    """The source lands in a small quadrilateral of a large output: most tiles
+    have every tap outside (constant fill), the rest interpolate."""
+    for c in (3, 4):
+        img = wl.uniform_u8(240, 320, c, seed=90 + c)
+        m = np.array([[0.3, 0.05, 140.0], [0.02, 0.35, 90.0], [2e-4, 1e-4, 1.0]])
+        check(img, m, 600, 800, f"mostly border c={c}", border=CONST, bval=77)
