@@ -28,7 +28,11 @@ __global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict
 {
     extern __shared__ uint32_t lds[];
     TileSeq seq(blockIdx.x, gridDim.x, ntiles);
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT, false>(G, e, lds, [&](TiledJob &t, int &tile) {
+    // f32 outputs leave through non-temporal stores: faster here, where each
+    // tile writes rows of a small image; the single-image kernels keep plain
+    // stores, under which a reused output buffer stays partly in the
+    // last-level cache
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, false>(G, e, lds, [&](TiledJob &t, int &tile) {
         int g;
         if (!seq.take(g))
             return false;

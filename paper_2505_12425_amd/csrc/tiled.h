@@ -277,24 +277,35 @@ __device__ __forceinline__ void store_u8_4(uint8_t *p, int n, bool aligned, cons
     }
 }
 
-template <int C>
+// f32 vector store; NT: non-temporal (streaming) store, for outputs that no
+// later kernel of the launch reads.
+template <bool NT, typename V>
+__device__ __forceinline__ void put(V *q, V v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, q);
+    else
+        *q = v;
+}
+
+template <int C, bool NT = false>
 __device__ __forceinline__ void store_f32_4(float *p, int n, bool aligned, const float (&o)[4][C])
 {
     if (n == 4 && aligned) {
         f32x4 *q = reinterpret_cast<f32x4 *>(p);
         if constexpr (C == 3) {
-            q[0] = f32x4{o[0][0], o[0][1], o[0][2], o[1][0]};
-            q[1] = f32x4{o[1][1], o[1][2], o[2][0], o[2][1]};
-            q[2] = f32x4{o[2][2], o[3][0], o[3][1], o[3][2]};
+            put<NT>(q + 0, f32x4{o[0][0], o[0][1], o[0][2], o[1][0]});
+            put<NT>(q + 1, f32x4{o[1][1], o[1][2], o[2][0], o[2][1]});
+            put<NT>(q + 2, f32x4{o[2][2], o[3][0], o[3][1], o[3][2]});
         } else if constexpr (C == 4) {
 #pragma unroll
             for (int k = 0; k < 4; k++)
-                q[k] = f32x4{o[k][0], o[k][1], o[k][2], o[k][3]};
+                put<NT>(q + k, f32x4{o[k][0], o[k][1], o[k][2], o[k][3]});
         } else if constexpr (C == 2) {
-            q[0] = f32x4{o[0][0], o[0][1], o[1][0], o[1][1]};
-            q[1] = f32x4{o[2][0], o[2][1], o[3][0], o[3][1]};
+            put<NT>(q + 0, f32x4{o[0][0], o[0][1], o[1][0], o[1][1]});
+            put<NT>(q + 1, f32x4{o[2][0], o[2][1], o[3][0], o[3][1]});
         } else {
-            q[0] = f32x4{o[0][0], o[1][0], o[2][0], o[3][0]};
+            put<NT>(q, f32x4{o[0][0], o[1][0], o[2][0], o[3][0]});
         }
     } else {
         for (int k = 0; k < n; k++)
@@ -337,16 +348,23 @@ __device__ __forceinline__ void store_u8_px(uint8_t *row, int x, int x_end, bool
     }
 }
 
-template <int C>
+template <int C, bool NT = false>
 __device__ __forceinline__ void store_f32_px(float *row, int x, int x_end, const float (&o)[C])
 {
     if (x >= x_end)
         return;
     if constexpr (C == 3) {
-        struct __attribute__((packed, aligned(4))) F3 { float a, b, c; };
-        *reinterpret_cast<F3 *>(row + 3 * (size_t)x) = F3{o[0], o[1], o[2]};
+        float *q = row + 3 * (size_t)x;
+        if constexpr (NT) {  // three adjacent dwords: one 12-byte store
+            put<true>(q, o[0]);
+            put<true>(q + 1, o[1]);
+            put<true>(q + 2, o[2]);
+        } else {
+            struct __attribute__((packed, aligned(4))) F3 { float a, b, c; };
+            *reinterpret_cast<F3 *>(q) = F3{o[0], o[1], o[2]};
+        }
     } else {
-        *reinterpret_cast<f32x4 *>(row + 4 * (size_t)x) = f32x4{o[0], o[1], o[2], o[3]};
+        put<NT>(reinterpret_cast<f32x4 *>(row + 4 * (size_t)x), f32x4{o[0], o[1], o[2], o[3]});
     }
 }
 
@@ -361,14 +379,14 @@ __device__ __forceinline__ void store_run_u8(uint8_t *row, int x, int x_end, boo
         store_u8_px<C>(row, x, x_end, aligned, P[0], sel);
 }
 
-template <int C, int PX>
+template <int C, int PX, bool NT = false>
 __device__ __forceinline__ void store_run_f32(float *row, int x, int x_end, bool aligned, const float (&o)[PX][C])
 {
     if constexpr (PX == 4) {
         if (x < x_end)
-            store_f32_4<C>(row + (size_t)x * C, min(4, x_end - x), aligned, o);
+            store_f32_4<C, NT>(row + (size_t)x * C, min(4, x_end - x), aligned, o);
     } else {
-        store_f32_px<C>(row, x, x_end, o[0]);
+        store_f32_px<C, NT>(row, x, x_end, o[0]);
     }
 }
 
@@ -404,12 +422,12 @@ __device__ __forceinline__ void store_row_u8(const ImageJob &j, bool planar, int
     }
 }
 
-template <int C, int PX>
+template <int C, int PX, bool NT = false>
 __device__ __forceinline__ void store_row_f32(const ImageJob &j, bool planar, int y, int x, int x_end, bool aligned,
                                               const float (&o)[PX][C])
 {
     if (!planar) {
-        store_run_f32<C, PX>(static_cast<float *>(j.dst) + (size_t)y * (size_t)j.dw * C, x, x_end, aligned, o);
+        store_run_f32<C, PX, NT>(static_cast<float *>(j.dst) + (size_t)y * (size_t)j.dw * C, x, x_end, aligned, o);
         return;
     }
     const size_t plane = (size_t)j.dh * (size_t)j.dw;
@@ -421,12 +439,12 @@ __device__ __forceinline__ void store_row_f32(const ImageJob &j, bool planar, in
     for (int c = 0; c < C; c++) {
         if constexpr (PX == 4) {
             if (n == 4 && (j.dw & 3) == 0) {
-                *reinterpret_cast<f32x4 *>(row + c * plane) = f32x4{o[0][c], o[1][c], o[2][c], o[3][c]};
+                put<NT>(reinterpret_cast<f32x4 *>(row + c * plane), f32x4{o[0][c], o[1][c], o[2][c], o[3][c]});
                 continue;
             }
         }
         for (int k = 0; k < n; k++)
-            row[c * plane + k] = o[k][c];
+            put<NT>(row + c * plane + k, o[k][c]);
     }
 }
 
@@ -788,9 +806,10 @@ __device__ __forceinline__ void resize_tables(const TiledJob &t, const Plan &p, 
 // per lane, 256 / TXT apart.  Tile = (TXT * PX * CPT) x ((256 / TXT) * RPT).
 // Pixels past the tile's right edge are computed as its last column (PX = 1
 // keeps every lane in the quad exchange) and not stored.
-template <int PX_, int TXT_, int CPT_, int RPT_> struct Layout {
+template <int PX_, int TXT_, int CPT_, int RPT_, bool NT_ = false> struct Layout {
     static_assert(PX_ == 4 || (PX_ == 1 && TXT_ == 64), "one-pixel runs need whole-wave rows");
     static constexpr int PX = PX_, TXT = TXT_, CPT = CPT_, RPT = RPT_;
+    static constexpr bool NT = NT_;  // f32 output through non-temporal stores
     static constexpr int SEG = TXT * PX;             // columns between a lane's runs
     static constexpr int TW = SEG * CPT;
     static constexpr int ROWS = KT_THREADS / TXT;    // tile rows per pass
@@ -910,7 +929,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                     interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
                                   e, o[k]);
                 }
-                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
             }
         }
     }
@@ -1002,7 +1021,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                     interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
                                   e, o[k]);
                 }
-                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
             }
         }
     }
@@ -1208,7 +1227,7 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
             if constexpr (!F32)
                 store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
             else
-                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
         }
     }
 }
@@ -1245,7 +1264,7 @@ __device__ __forceinline__ void fill_blank(const TiledJob &t, const Plan &p, con
             if constexpr (!F32)
                 store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
             else
-                store_row_f32<C, PX>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
         }
     }
 }
