@@ -34,7 +34,16 @@ namespace kr {
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int KT_THREADS = 256;
-constexpr int KT_MARGIN = 16;  // LDS dwords kept free on each side of a box row
+// LDS box rows.  Staging writes whole 16-pixel groups aligned on the source's
+// pixel numbering, so a row's writes reach up to KT_SPILL pixels before and
+// after its box.  Row s of the box starts at dword s * pitch + KT_MARGIN; with
+// pitch >= box width + KT_SPILL one row's spill ends before the next row's
+// box begins and starts after the previous row's box ends (neighbouring
+// spills may overlap: they hold pixels nobody reads).  KT_MARGIN dwords
+// before row 0 take its left spill; the last row's right spill stays inside
+// its own pitch.
+constexpr int KT_MARGIN = 16;
+constexpr int KT_SPILL = 15;
 
 // Per-image parameters of the tiled kernels.
 struct TiledJob {
@@ -451,7 +460,7 @@ __device__ __forceinline__ void store_row_f32(const ImageJob &j, bool planar, in
 // ------------------------------------------------------------------ tile plan
 // Launch-wide LDS geometry: every tile of a launch stages into rows x pitch dwords.
 struct TileGeom {
-    int pitch;  // LDS row pitch in dwords (>= box width + 2 * KT_MARGIN)
+    int pitch;  // LDS row pitch in dwords (>= box width + KT_SPILL)
     int rows;   // LDS rows (box rows for warps, 2 * tile height for resizes)
 };
 
@@ -592,7 +601,7 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
     }
     p.bx0 = x0min;
     p.bw = x0max + 2 - x0min;
-    p.direct = !persp_ok || p.bw + 2 * KT_MARGIN > G.pitch || p.nslots > G.rows;
+    p.direct = !persp_ok || p.bw + KT_SPILL > G.pitch || p.nslots > G.rows;
     // The bounds hold every pixel's top-left tap (x0, y0); its taps are x0,
     // x0 + 1 and y0, y0 + 1.  If all of them fall left of, right of, above or
     // below the image, every tap reads the border constant, whose weights sum
@@ -784,7 +793,7 @@ template <int TW, int TH, bool F32>
 __device__ __forceinline__ void resize_tables(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds)
 {
     const ImageJob &j = t.j;
-    uint32_t *tab = lds + G.rows * G.pitch;
+    uint32_t *tab = lds + G.rows * G.pitch + KT_MARGIN;
     for (int i = threadIdx.x; i < TW + TH; i += KT_THREADS) {
         int i0, w1;
         float f;
@@ -954,7 +963,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
     constexpr int PX = L::PX, CPT = L::CPT, TW = L::TW, TH = L::TH;
     const ImageJob &j = t.j;
     const int H = j.sh, W = j.sw;
-    const uint32_t *tab = lds + G.rows * G.pitch;
+    const uint32_t *tab = lds + G.rows * G.pitch + KT_MARGIN;
     const int pitch = G.pitch;
     const bool aligned = layout_aligned<C, F32, L>(j.dw);
     const uint32_t sel = quad_selector(lane_id() & 3);
@@ -1145,7 +1154,7 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
     const bool aligned = layout_aligned<C, F32, L>(j.dw);
     const uint32_t sel = quad_selector(lane_id() & 3);
     const int x_end = p.ox1 + 1;
-    const uint32_t *tab = lds + G.rows * G.pitch;
+    const uint32_t *tab = lds + G.rows * G.pitch + KT_MARGIN;
     double m[6];
 #pragma unroll
     for (int i = 0; i < 6; i++)

@@ -205,7 +205,7 @@ static TileGeom persp_geom(const ImageJob &j, int tw, int th)
                 if (bx.bw < 0)
                     continue;
                 const int bw = bx.bw + 6, bh = bx.bh + 6;
-                if ((size_t)bank_pitch(bw + 2 * KT_MARGIN) * bh * 4 + (size_t)(2 * tw + 2 * th) * 4 > KT_LDS_CAP)
+                if (tile_lds_bytes(TileGeom{bank_pitch(bw + KT_SPILL), bh}, tw, th) > KT_LDS_CAP)
                     continue;
                 maxw = std::max(maxw, bw);
                 maxh = std::max(maxh, bh);
@@ -213,7 +213,7 @@ static TileGeom persp_geom(const ImageJob &j, int tw, int th)
         }
     }
     TileGeom G;
-    G.pitch = maxw > 0 ? bank_pitch(maxw + 2 * KT_MARGIN) : 0;
+    G.pitch = maxw > 0 ? bank_pitch(maxw + KT_SPILL) : 0;
     G.rows = maxh;
     return G;
 }
@@ -226,12 +226,12 @@ TileGeom tile_geom(const ImageJob &j, int op, int tw, int th)
     if (op == OP_WARP) {
         const double ex = std::fabs(j.inv[0]) * (tw - 1) + std::fabs(j.inv[1]) * (th - 1);
         const double ey = std::fabs(j.inv[3]) * (tw - 1) + std::fabs(j.inv[4]) * (th - 1);
-        G.pitch = (int)std::fmin(std::ceil(ex) + 4.0, (double)j.sw + 6.0) + 2 * KT_MARGIN;
+        G.pitch = (int)std::fmin(std::ceil(ex) + 4.0, (double)j.sw + 6.0) + KT_SPILL;
         G.rows = (int)std::fmin(std::ceil(ey) + 4.0, (double)j.sh + 6.0);
         G.pitch = bank_pitch(G.pitch);
     } else {
         const double rx = (double)j.sw / (double)j.dw;
-        G.pitch = (int)std::fmin(std::ceil(rx * (tw - 1)) + 3.0, (double)j.sw + 4.0) + 2 * KT_MARGIN;
+        G.pitch = (int)std::fmin(std::ceil(rx * (tw - 1)) + 3.0, (double)j.sw + 4.0) + KT_SPILL;
         G.rows = 2 * th;
         G.pitch = bank_pitch(G.pitch);
     }
@@ -247,7 +247,8 @@ bool wants_gather(const ImageJob &j, int op)
 
 size_t tile_lds_bytes(const TileGeom &G, int tw, int th)
 {
-    return (size_t)G.rows * G.pitch * 4 + (size_t)(2 * tw + 2 * th) * 4;
+    // box rows, the margin before row 0, then the resize tables
+    return ((size_t)G.rows * G.pitch + KT_MARGIN) * 4 + (size_t)(2 * tw + 2 * th) * 4;
 }
 
 template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
