@@ -160,9 +160,15 @@ void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const Til
         else
             P = default_batch_cfg(op, f32);
         if (op == OP_RESIZE) {
+            // An item that shrinks x by 2 or more shares no taps between
+            // neighbouring outputs, while its box (over twice the tile width)
+            // would set the LDS size of every workgroup of the launch: such
+            // items read their taps directly, which keeps the group's LDS and
+            // so its occupancy at the size the milder items need.
             std::vector<bool> stage;
             for (const ImageJob &j : imgs[k])
-                stage.push_back(!wants_gather(j, op) && fits(j, op, P, KB_LDS_BUDGET));
+                stage.push_back(!wants_gather(j, op) && (double)j.sw < 2.0 * (double)j.dw &&
+                                fits(j, op, P, KB_LDS_BUDGET));
             b.groups.emplace_back();
             b.tables.emplace_back();
             build_group(op, P, false, imgs[k], stage, b.groups.back(), b.tables.back());
