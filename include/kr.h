@@ -199,6 +199,11 @@ kr_status kr_warp_perspective_view(const void *src, int src_h, int src_w, size_t
 kr_status kr_resize_nearest_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
                                  void *dst, int dst_h, int dst_w, kr_dtype dst_t,
                                  const kr_normalize *norm, void *stream);
+/* Flip and RGB -> gray of a source view; the destination (h x w) is contiguous. */
+kr_status kr_flip_view(const void *src, int h, int w, size_t src_pitch, int c, kr_dtype t,
+                       void *dst, int flip_x, int flip_y, void *stream);
+kr_status kr_rgb_to_gray_view(const void *src, int h, int w, size_t src_pitch, kr_dtype src_t,
+                              void *dst, kr_dtype dst_t, const kr_normalize *norm, void *stream);
 
 /* One image of a batch.  op: 0 = resize, 1 = warp.  m and flags are read for
  * warps only (same meaning as in kr_warp_affine).  src_pitch: bytes between

@@ -281,28 +281,38 @@ kr_status kr_resize_nearest(const void *src, int src_h, int src_w, int c, kr_dty
     return kr_resize_nearest_view(src, src_h, src_w, 0, c, src_t, dst, dst_h, dst_w, dst_t, norm, stream);
 }
 
-kr_status kr_flip(const void *src, int h, int w, int c, kr_dtype t, void *dst, int flip_x, int flip_y, void *stream)
+kr_status kr_flip_view(const void *src, int h, int w, size_t src_pitch, int c, kr_dtype t, void *dst, int flip_x,
+                       int flip_y, void *stream)
 {
     clear_error();
-    kr_status s = check_common(src, h, w, c, t, dst, h, w, t, KR_BORDER_REPLICATE, 0.0f, nullptr);
+    kr_status s = check_common(src, h, w, c, t, dst, h, w, t, KR_BORDER_REPLICATE, 0.0f, nullptr, src_pitch);
     if (s != KR_OK)
         return s;
     if ((flip_x != 0 && flip_x != 1) || (flip_y != 0 && flip_y != 1))
         return fail(KR_ERR_INVALID_ARGUMENT, "flip flags must be 0 or 1");
-    const hipError_t err = launch_flip(c, t, src, dst, h, w, flip_x, flip_y, (hipStream_t)stream);
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    set_source(j, src, h, w, c, t, src_pitch);
+    j.dst = dst; j.dh = h; j.dw = w;
+    const hipError_t err = launch_flip(c, t, j, flip_x, flip_y, (hipStream_t)stream);
     if (err != hipSuccess)
         return fail(KR_ERR_HIP, "flip launch failed: %s", hipGetErrorString(err));
     return KR_OK;
 }
 
-kr_status kr_rgb_to_gray(const void *src, int h, int w, kr_dtype src_t, void *dst, kr_dtype dst_t,
-                         const kr_normalize *norm, void *stream)
+kr_status kr_flip(const void *src, int h, int w, int c, kr_dtype t, void *dst, int flip_x, int flip_y, void *stream)
+{
+    return kr_flip_view(src, h, w, 0, c, t, dst, flip_x, flip_y, stream);
+}
+
+kr_status kr_rgb_to_gray_view(const void *src, int h, int w, size_t src_pitch, kr_dtype src_t, void *dst,
+                              kr_dtype dst_t, const kr_normalize *norm, void *stream)
 {
     clear_error();
     if (!((src_t == KR_U8 && dst_t == KR_U8) || (src_t == KR_U8 && dst_t == KR_F32) ||
           (src_t == KR_F32 && dst_t == KR_F32)))
         return fail(KR_ERR_UNSUPPORTED, "dtype pair (%d -> %d) not supported", (int)src_t, (int)dst_t);
-    kr_status s = check_image("src", src, h, w, 3);
+    kr_status s = check_source(src, h, w, 3, src_t, src_pitch);
     if (s == KR_OK)
         s = check_image("dst", dst, h, w, 1);
     if (s != KR_OK)
@@ -314,15 +324,25 @@ kr_status kr_rgb_to_gray(const void *src, int h, int w, kr_dtype src_t, void *ds
             return fail(KR_ERR_INVALID_ARGUMENT, "normalisation has a bad mean/std");
     }
     const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
-    const uintptr_t s1 = s0 + (uintptr_t)h * (uintptr_t)w * 3 * elem_size(src_t);
+    const uintptr_t s1 = s0 + source_span(h, w, 3, src_t, src_pitch);
     const uintptr_t d1 = d0 + (uintptr_t)h * (uintptr_t)w * elem_size(dst_t);
     if (s0 < d1 && d0 < s1)
         return fail(KR_ERR_INVALID_ARGUMENT, "src and dst overlap");
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    set_source(j, src, h, w, 3, src_t, src_pitch);
+    j.dst = dst; j.dh = h; j.dw = w;
     const Epilogue e = make_epilogue(1, KR_BORDER_REPLICATE, 0.0f, norm);
-    const hipError_t err = launch_gray(src_t, dst_t, src, dst, h, w, e, (hipStream_t)stream);
+    const hipError_t err = launch_gray(src_t, dst_t, j, e, (hipStream_t)stream);
     if (err != hipSuccess)
         return fail(KR_ERR_HIP, "gray launch failed: %s", hipGetErrorString(err));
     return KR_OK;
+}
+
+kr_status kr_rgb_to_gray(const void *src, int h, int w, kr_dtype src_t, void *dst, kr_dtype dst_t,
+                         const kr_normalize *norm, void *stream)
+{
+    return kr_rgb_to_gray_view(src, h, w, 0, src_t, dst, dst_t, norm, stream);
 }
 
 // Inverse of a 3x3 homography by the adjugate (fixed evaluation order:

@@ -55,10 +55,9 @@ hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const
 hipError_t launch_persp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
                         hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
-// Flip and RGB -> gray (pointops.hip).
-hipError_t launch_flip(int c, kr_dtype t, const void *src, void *dst, int h, int w, int fx, int fy, hipStream_t s);
-hipError_t launch_gray(kr_dtype st, kr_dtype dt, const void *src, void *dst, int h, int w, const Epilogue &e,
-                       hipStream_t s);
+// Flip and RGB -> gray (pointops.hip); the destination is contiguous, sh x sw.
+hipError_t launch_flip(int c, kr_dtype t, const ImageJob &j, int fx, int fy, hipStream_t s);
+hipError_t launch_gray(kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
 // Nearest-neighbour resize (nearest.hip); any channel count and type pair.
 hipError_t launch_nearest(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
 

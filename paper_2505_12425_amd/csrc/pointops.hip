@@ -16,6 +16,15 @@ namespace {
 
 constexpr int PO_TX = 64, PO_TY = 4, PO_RPT = 2;
 
+// Source and destination of one flip or gray launch.  Source pixel (x, y) is
+// pixel number sk + y * sp + x from src (as in ImageJob); the destination is
+// contiguous, w pixels per row.
+struct PtJob {
+    const void *src;
+    void *dst;
+    int h, w, sp, sk;
+};
+
 // Pixels lin .. lin + 3 of a u8 image with C channels (byte c = channel c),
 // for lin a multiple of 4: one 4-, 8-, 12- or 16-byte aligned load.
 template <int C>
@@ -43,15 +52,19 @@ __device__ __forceinline__ void load_run4(const uint8_t *__restrict__ src, size_
 
 // ---------------------------------------------------------------- flip
 template <int C>
-__global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_u8(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
-                                                          int h, int w, int fx, int fy)
+__global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_u8(PtJob j, int fx, int fy)
 {
+    const uint8_t *__restrict__ src = static_cast<const uint8_t *>(j.src);
+    uint8_t *__restrict__ dst = static_cast<uint8_t *>(j.dst);
+    const int h = j.h, w = j.w;
     const int x = (blockIdx.x * PO_TX + threadIdx.x) * 4;
     if (x >= w)
         return;
     const int n = min(4, w - x);
-    const size_t nbytes = (size_t)h * w * C;
+    const size_t nbytes = ((size_t)j.sk + (size_t)(h - 1) * j.sp + w) * C;
     const bool aligned = store4_aligned<C, false>(w);
+    // 4-pixel source runs start on multiples of 4 pixels from src
+    const bool runs = (w & 3) == 0 && ((j.sp | j.sk) & 3) == 0;
     int sx[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
@@ -63,9 +76,9 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_u8(const uint8_t *__rest
         const int y = blockIdx.y * (PO_TY * PO_RPT) + threadIdx.y + rr * PO_TY;
         if (y >= h)
             break;
-        const size_t row = (size_t)(fy ? h - 1 - y : y) * w;
+        const size_t row = (size_t)j.sk + (size_t)(fy ? h - 1 - y : y) * j.sp;
         uint32_t P[4];
-        if (n == 4 && (w & 3) == 0) {
+        if (n == 4 && runs) {
             // the four source pixels are one aligned run (reversed when fx)
             uint32_t R[4];
             load_run4<C>(src, row + (size_t)min(sx[0], sx[3]), R);
@@ -83,9 +96,11 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_u8(const uint8_t *__rest
 
 // f32: the samples' bits are moved unchanged (one pixel per thread).
 template <int C>
-__global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_f32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
-                                                           int h, int w, int fx, int fy)
+__global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_f32(PtJob j, int fx, int fy)
 {
+    const uint32_t *__restrict__ src = static_cast<const uint32_t *>(j.src);
+    uint32_t *__restrict__ dst = static_cast<uint32_t *>(j.dst);
+    const int h = j.h, w = j.w;
     const int x = blockIdx.x * PO_TX + threadIdx.x;
     if (x >= w)
         return;
@@ -95,7 +110,7 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_f32(const uint32_t *__re
         const int y = blockIdx.y * (PO_TY * 4 * PO_RPT) + threadIdx.y + rr * PO_TY;
         if (y >= h)
             break;
-        const uint32_t *s = src + ((size_t)(fy ? h - 1 - y : y) * w + sx) * C;
+        const uint32_t *s = src + ((size_t)j.sk + (size_t)(fy ? h - 1 - y : y) * j.sp + sx) * C;
         uint32_t *d = dst + ((size_t)y * w + x) * C;
         if constexpr (C == 3) {
             struct __attribute__((packed, aligned(4))) W3 { uint32_t a, b, c; };
@@ -122,26 +137,30 @@ __device__ __forceinline__ float gray_f32(float r, float g, float b, const Epilo
 }
 
 template <bool SRC_F32, bool DST_F32>
-__global__ __launch_bounds__(PO_TX * PO_TY) void k_gray(const void *__restrict__ src, void *__restrict__ dst, int h,
-                                                       int w, Epilogue e)
+__global__ __launch_bounds__(PO_TX * PO_TY) void k_gray(PtJob j, Epilogue e)
 {
+    const void *__restrict__ src = j.src;
+    void *__restrict__ dst = j.dst;
+    const int h = j.h, w = j.w;
     const int x = (blockIdx.x * PO_TX + threadIdx.x) * 4;
     if (x >= w)
         return;
     const int n = min(4, w - x);
-    const size_t nbytes = (size_t)h * w * 3 * (SRC_F32 ? 4 : 1);
+    const size_t nbytes = ((size_t)j.sk + (size_t)(h - 1) * j.sp + w) * 3 * (SRC_F32 ? 4 : 1);
+    const bool runs = ((j.sp | j.sk) & 3) == 0;  // 4-pixel source runs start on multiples of 4
 #pragma unroll
     for (int rr = 0; rr < PO_RPT; rr++) {
         const int y = blockIdx.y * (PO_TY * PO_RPT) + threadIdx.y + rr * PO_TY;
         if (y >= h)
             break;
-        const size_t lin = (size_t)y * w + x;
+        const size_t lin = (size_t)y * w + x;                      // destination pixel
+        const size_t slin = (size_t)j.sk + (size_t)y * j.sp + x;   // source pixel
         float o[4];
         uint32_t g[4];
         if constexpr (!SRC_F32) {
-            if (n == 4 && (w & 3) == 0) {
+            if (n == 4 && runs) {
                 uint32_t P[4];
-                load_run4<3>(static_cast<const uint8_t *>(src), lin, P);
+                load_run4<3>(static_cast<const uint8_t *>(src), slin, P);
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     if constexpr (DST_F32)
@@ -155,7 +174,7 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_gray(const void *__restrict__
         }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const size_t q = lin + (size_t)min(k, n - 1);
+            const size_t q = slin + (size_t)min(k, n - 1);
             if constexpr (SRC_F32) {
                 const float *s = static_cast<const float *>(src) + q * 3;
                 o[k] = gray_f32(s[0], s[1], s[2], e);
@@ -190,44 +209,42 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_gray(const void *__restrict__
 
 }  // namespace
 
-hipError_t launch_flip(int c, kr_dtype t, const void *src, void *dst, int h, int w, int fx, int fy, hipStream_t s)
+hipError_t launch_flip(int c, kr_dtype t, const ImageJob &ij, int fx, int fy, hipStream_t s)
 {
+    const PtJob j{ij.src, ij.dst, ij.sh, ij.sw, ij.sp, ij.sk};
+    const int h = j.h, w = j.w;
     const dim3 block(PO_TX, PO_TY);
     if (t == KR_U8) {
         const dim3 grid((w + 4 * PO_TX - 1) / (4 * PO_TX), (h + PO_TY * PO_RPT - 1) / (PO_TY * PO_RPT));
-        const uint8_t *sp = static_cast<const uint8_t *>(src);
-        uint8_t *dp = static_cast<uint8_t *>(dst);
         switch (c) {
-        case 1: hipLaunchKernelGGL(k_flip_u8<1>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
-        case 2: hipLaunchKernelGGL(k_flip_u8<2>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
-        case 3: hipLaunchKernelGGL(k_flip_u8<3>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
-        default: hipLaunchKernelGGL(k_flip_u8<4>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
+        case 1: hipLaunchKernelGGL(k_flip_u8<1>, grid, block, 0, s, j, fx, fy); break;
+        case 2: hipLaunchKernelGGL(k_flip_u8<2>, grid, block, 0, s, j, fx, fy); break;
+        case 3: hipLaunchKernelGGL(k_flip_u8<3>, grid, block, 0, s, j, fx, fy); break;
+        default: hipLaunchKernelGGL(k_flip_u8<4>, grid, block, 0, s, j, fx, fy); break;
         }
     } else {
         const dim3 grid((w + PO_TX - 1) / PO_TX, (h + 4 * PO_TY * PO_RPT - 1) / (4 * PO_TY * PO_RPT));
-        const uint32_t *sp = static_cast<const uint32_t *>(src);
-        uint32_t *dp = static_cast<uint32_t *>(dst);
         switch (c) {
-        case 1: hipLaunchKernelGGL(k_flip_f32<1>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
-        case 2: hipLaunchKernelGGL(k_flip_f32<2>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
-        case 3: hipLaunchKernelGGL(k_flip_f32<3>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
-        default: hipLaunchKernelGGL(k_flip_f32<4>, grid, block, 0, s, sp, dp, h, w, fx, fy); break;
+        case 1: hipLaunchKernelGGL(k_flip_f32<1>, grid, block, 0, s, j, fx, fy); break;
+        case 2: hipLaunchKernelGGL(k_flip_f32<2>, grid, block, 0, s, j, fx, fy); break;
+        case 3: hipLaunchKernelGGL(k_flip_f32<3>, grid, block, 0, s, j, fx, fy); break;
+        default: hipLaunchKernelGGL(k_flip_f32<4>, grid, block, 0, s, j, fx, fy); break;
         }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gray(kr_dtype st, kr_dtype dt, const void *src, void *dst, int h, int w, const Epilogue &e,
-                       hipStream_t s)
+hipError_t launch_gray(kr_dtype st, kr_dtype dt, const ImageJob &ij, const Epilogue &e, hipStream_t s)
 {
+    const PtJob j{ij.src, ij.dst, ij.sh, ij.sw, ij.sp, ij.sk};
     const dim3 block(PO_TX, PO_TY);
-    const dim3 grid((w + 4 * PO_TX - 1) / (4 * PO_TX), (h + PO_TY * PO_RPT - 1) / (PO_TY * PO_RPT));
+    const dim3 grid((j.w + 4 * PO_TX - 1) / (4 * PO_TX), (j.h + PO_TY * PO_RPT - 1) / (PO_TY * PO_RPT));
     if (st == KR_F32)
-        hipLaunchKernelGGL((k_gray<true, true>), grid, block, 0, s, src, dst, h, w, e);
+        hipLaunchKernelGGL((k_gray<true, true>), grid, block, 0, s, j, e);
     else if (dt == KR_F32)
-        hipLaunchKernelGGL((k_gray<false, true>), grid, block, 0, s, src, dst, h, w, e);
+        hipLaunchKernelGGL((k_gray<false, true>), grid, block, 0, s, j, e);
     else
-        hipLaunchKernelGGL((k_gray<false, false>), grid, block, 0, s, src, dst, h, w, e);
+        hipLaunchKernelGGL((k_gray<false, false>), grid, block, 0, s, j, e);
     return hipGetLastError();
 }
 

@@ -83,6 +83,10 @@ def lib():
     L.kr_warp_perspective_view.restype = i
     L.kr_resize_nearest_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, i, npp, vp]
     L.kr_resize_nearest_view.restype = i
+    L.kr_flip_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, vp]
+    L.kr_flip_view.restype = i
+    L.kr_rgb_to_gray_view.argtypes = [vp, i, i, sz_, i, vp, i, npp, vp]
+    L.kr_rgb_to_gray_view.restype = i
     L.kr_invert_homography.argtypes = [dp, dp]
     L.kr_invert_homography.restype = i
     L.kr_flip.argtypes = [vp, i, i, i, i, vp, i, i, vp]
@@ -243,21 +247,27 @@ def resize_nearest(src, dst, mean=None, std=None, stream=None) -> None:
 
 
 def flip(src, dst, flip_x: bool = True, flip_y: bool = False, stream=None) -> None:
-    """kr_flip on torch tensors of the same shape and dtype."""
-    sp, h, w, c, st = _image(src)
+    """kr_flip on torch tensors of the same shape and dtype (src may be a view)."""
+    sp, h, w, pitch, c, st = _source(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if (dh, dw, dc, dt) != (h, w, c, st):
         raise ValueError("flip needs src and dst of the same shape and dtype")
-    check(lib().kr_flip(sp, h, w, c, st, dp_, int(flip_x), int(flip_y), _stream(stream)))
+    if pitch:
+        check(lib().kr_flip_view(sp, h, w, pitch, c, st, dp_, int(flip_x), int(flip_y), _stream(stream)))
+    else:
+        check(lib().kr_flip(sp, h, w, c, st, dp_, int(flip_x), int(flip_y), _stream(stream)))
 
 
 def rgb_to_gray(src, dst, mean=None, std=None, stream=None) -> None:
-    """kr_rgb_to_gray: src HxWx3 -> dst HxW(x1)."""
-    sp, h, w, c, st = _image(src)
+    """kr_rgb_to_gray: src HxWx3 (may be a view) -> dst HxW(x1)."""
+    sp, h, w, pitch, c, st = _source(src)
     dp_, dh, dw, dc, dt = _image(dst)
     if c != 3 or dc != 1 or (dh, dw) != (h, w):
         raise ValueError("rgb_to_gray needs HxWx3 -> HxWx1")
-    check(lib().kr_rgb_to_gray(sp, h, w, st, dp_, dt, _normalize(mean, std, 1), _stream(stream)))
+    if pitch:
+        check(lib().kr_rgb_to_gray_view(sp, h, w, pitch, st, dp_, dt, _normalize(mean, std, 1), _stream(stream)))
+    else:
+        check(lib().kr_rgb_to_gray(sp, h, w, st, dp_, dt, _normalize(mean, std, 1), _stream(stream)))
 
 
 def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, border_value: float = 0.0,

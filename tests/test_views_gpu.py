@@ -179,3 +179,42 @@ def test_batch_items_with_views():
         torch.cuda.synchronize()
         for i, (sp, ref) in enumerate(zip(specs, refs)):
             assert torch.equal(sp["dst"].view(torch.uint8), ref.view(torch.uint8)), f"batch item {i} {out}"
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 4])
+def test_view_flip(c):
+    for k, ((ph, pw), crop) in enumerate(CROPS):
+        for f32 in (False, True):
+            par, view, host = parent_and_view(ph, pw, c, crop, f32=f32, seed=k)
+            for fx, fy in ((1, 0), (0, 1), (1, 1)):
+                what = f"flip c={c} f32={f32} ({fx},{fy}) crop {crop}"
+                say(what)
+                d = torch.empty(host.shape, dtype=view.dtype, device="cuda")
+                kr.flip(view, d, bool(fx), bool(fy))
+                torch.cuda.synchronize()
+                got = d.cpu().numpy()
+                exp = oracle.flip(host, bool(fx), bool(fy))
+                assert np.array_equal(got.view(np.uint8), exp.view(np.uint8)), what
+
+
+def test_view_gray():
+    mean, std = (0.45,), (0.25,)
+    for k, ((ph, pw), crop) in enumerate(CROPS):
+        for f32 in (False, True):
+            par, view, host = parent_and_view(ph, pw, 3, crop, f32=f32, seed=k)
+            h, w = host.shape[:2]
+            for out in (("f32",) if f32 else ("u8", "f32")):
+                what = f"gray f32src={f32} out={out} crop {crop}"
+                say(what)
+                d = empty(h, w, 1, out)
+                if out == "f32":
+                    kr.rgb_to_gray(view, d, mean, std)
+                else:
+                    kr.rgb_to_gray(view, d)
+                torch.cuda.synchronize()
+                got = d.cpu().numpy()
+                if out == "u8":
+                    assert_u8_equal(got, oracle.rgb_to_gray(host, "u8"), what)
+                else:
+                    exp = oracle.rgb_to_gray(host, "f64", mean, std)
+                    assert_f32_close(got, exp, what, std=std)
