@@ -65,7 +65,8 @@ kr_status check_source(const void *src, int h, int w, int c, kr_dtype st, size_t
     if (pitch < (size_t)w * px || pitch % px != 0)
         return fail(KR_ERR_INVALID_ARGUMENT, "src pitch %zu is not a whole number of pixels >= the row's %zu bytes",
                     pitch, (size_t)w * px);
-    if (15 + (size_t)(h - 1) * (pitch / px) + (size_t)w > (size_t)INT32_MAX - 16)
+    // (bounded first so that the span below cannot wrap)
+    if (pitch / px > (size_t)INT32_MAX || 15 + (size_t)(h - 1) * (pitch / px) + (size_t)w > (size_t)INT32_MAX - 16)
         return fail(KR_ERR_INVALID_ARGUMENT, "src view spans more than 2^31 - 32 pixels");
     return KR_OK;
 }

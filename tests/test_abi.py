@@ -358,8 +358,10 @@ def test_view_validation(fn):
     assert view_call(fn, 4 * 1000, src=A + 2, c=4) == inval
     # f32 RGB: 12-byte pixels; an address 2 bytes off the element grid fails
     assert view_call(fn, 12 * 1000, src=A + 2, st=kr.F32) == inval
-    # a view spanning more than 2^31 pixels
+    # a view spanning more than 2^31 pixels, and pitches whose span would wrap
     assert view_call(fn, 3 * 80000, sh=30000, sw=30000) == inval
+    assert view_call(fn, 3 * (1 << 62), sh=5) == inval
+    assert view_call(fn, 3 * ((1 << 31) + 1), sh=2) == inval
     # the view's span reaches the destination
     assert view_call(fn, 3 * 1000, dst=A + 16 * 18000) == inval  # inside rows 95..96 of the span
     assert "overlap" in kr.last_error()
