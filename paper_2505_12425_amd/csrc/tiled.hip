@@ -1,7 +1,6 @@
 // tiled.hip -- per-image launches of the LDS-tiled kernels (tiled.h): tile
 // shape, LDS budget and grid for one image.
 #include <algorithm>
-#include <vector>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -148,7 +147,8 @@ static TileGeom persp_geom(const ImageJob &j, int tw, int th)
         int tx0, tx1, ty0, ty1;  // tile range, half-open
         double ux, uy;           // bounds on the tiles' corner-image spans
     };
-    std::vector<Region> regs;
+    Region regs[16 * 16];  // on the stack: the launch path allocates nothing
+    int nreg = 0;
     for (int ry = 0; ry < ty_n; ry += rty) {
         for (int rx = 0; rx < tx_n; rx += rtx) {
             Region r{rx, std::min(rx + rtx, tx_n), ry, std::min(ry + rty, ty_n), 1e300, 1e300};
@@ -185,14 +185,14 @@ static TileGeom persp_geom(const ImageJob &j, int tw, int th)
                 r.ux = r.ux == r.ux ? r.ux : 1e300;  // w^2 underflow: no bound
                 r.uy = r.uy == r.uy ? r.uy : 1e300;
             }
-            regs.push_back(r);
+            regs[nreg++] = r;
         }
     }
     // regions with the largest bounds first, so the running maximum rises early
-    std::sort(regs.begin(), regs.end(),
-              [](const Region &p, const Region &q) { return p.ux + p.uy > q.ux + q.uy; });
+    std::sort(regs, regs + nreg, [](const Region &p, const Region &q) { return p.ux + p.uy > q.ux + q.uy; });
     int maxw = 0, maxh = 0;
-    for (const Region &r : regs) {
+    for (int ri = 0; ri < nreg; ri++) {
+        const Region &r = regs[ri];
         // floor(p) - floor(q) <= ceil(p - q): a region whose bound cannot beat
         // both maxima has no tile that would change them
         if (maxw > 0 && std::ceil(r.ux) + 6.0 <= (double)maxw && std::ceil(r.uy) + 6.0 <= (double)maxh)
