@@ -1,5 +1,6 @@
-// dispatch.hip -- chooses the kernel for one image: the LDS-tiled kernels for
-// u8 sources with 3 or 4 channels, the per-pixel kernels otherwise.
+// dispatch.hip -- chooses the kernel for one image: the exact-2x downscale
+// kernel where it applies, the LDS-tiled kernels for u8 sources with 3 or 4
+// channels, the per-pixel kernels otherwise.
 #include "kr_device.h"
 
 namespace kr {
@@ -9,6 +10,8 @@ hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epi
 
 hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
+    if (is_half_scale(st, j))
+        return launch_half(c, dt, j, e, s);
     if (tiled_supported(c, st))
         return launch_tiled(OP_RESIZE, c, dt, j, e, s);
     return launch_generic(OP_RESIZE, c, st, dt, j, e, s);

@@ -58,6 +58,10 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Flip and RGB -> gray (pointops.hip); the destination is contiguous, sh x sw.
 hipError_t launch_flip(int c, kr_dtype t, const ImageJob &j, int fx, int fy, hipStream_t s);
 hipError_t launch_gray(kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
+// Bilinear resize by exactly 2 in both axes from a u8 source (halfscale.hip):
+// the 2x2 block means, the same bits as the general kernels.
+bool is_half_scale(kr_dtype st, const ImageJob &j);
+hipError_t launch_half(int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
 // Nearest-neighbour resize (nearest.hip); any channel count and type pair.
 hipError_t launch_nearest(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
 

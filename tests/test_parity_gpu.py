@@ -13,12 +13,14 @@ import pytest
 
 import oracle
 from paper_2505_12425_amd import workloads as wl
-from tests.gpu_util import assert_f32_close, assert_u8_equal, gpu_resize, gpu_warp, say
+from tests.gpu_util import assert_f32_close, assert_u8_equal, dev, gpu_resize, gpu_warp, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_12425_amd import kr  # noqa: E402
 
 CONST, REPL = 0, 1
 MEAN, STD = wl.IMAGENET_MEAN, wl.IMAGENET_STD
@@ -161,6 +163,39 @@ def test_all_border_warp():
     say("all-border warp")
     got = gpu_warp(img, [1, 0, 1e6, 0, 1, -1e6], 40, 70, "u8", border=CONST, bval=42)
     assert (got == 42).all()
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 4])
+def test_exact_half_scale(c):
+    """Resizes by exactly 2 in both axes take the 2x2-mean kernel: sizes with
+    ragged 4-pixel groups, the smallest cases, both borders, and the last
+    bytes of the buffer (the byte-wise tail)."""
+    for h, w in ((2, 2), (2, 8), (4, 6), (34, 98), (62, 202), (480, 640), (301 * 2, 3 * 2)):
+        img = wl.uniform_u8(h, w, c, seed=h * w + c)
+        for border in (REPL, CONST):
+            check_resize(img, h // 2, w // 2, border, 9, what=f"half c={c}")
+
+
+def test_exact_half_scale_views():
+    """The 2x2-mean kernel on crops of a larger buffer (odd pixel offsets)."""
+    par = wl.uniform_u8(300, 500, 3, seed=123)
+    dev_par = dev(par)
+    for (y, x, h, w) in ((1, 3, 100, 202), (0, 0, 298, 498), (13, 7, 2, 2), (298, 490, 2, 10)):
+        view = dev_par[y:y + h, x:x + w]
+        host = np.ascontiguousarray(par[y:y + h, x:x + w])
+        for out in ("u8", "f32"):
+            say(f"half view {y},{x},{h}x{w} {out}")
+            d = torch.empty((h // 2, w // 2, 3), dtype=torch.uint8 if out == "u8" else torch.float32, device="cuda")
+            if out == "u8":
+                kr.resize(view, d, border=REPL)
+            else:
+                kr.resize(view, d, border=REPL, mean=MEAN, std=STD)
+            torch.cuda.synchronize()
+            if out == "u8":
+                assert_u8_equal(d.cpu().numpy(), oracle.resize(host, h // 2, w // 2, "u8", REPL, threads=TH), "half view")
+            else:
+                assert_f32_close(d.cpu().numpy(), oracle.resize(host, h // 2, w // 2, "f64", REPL, 0, MEAN, STD,
+                                                                threads=TH), "half view norm", std=STD)
 
 
 def test_blank_tiles_match_oracle():
