@@ -44,7 +44,7 @@ def kernel_source_sha() -> str:
 _TPL = re.compile(r"kr::k_(tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"
                   r"(?:, (?:true|false))?>")
 _OPS = {"0": "resize", "1": "warp", "2": "perspective"}
-_POINT = re.compile(r"kr::(?:\(anonymous namespace\)::)?k_(nearest|flip_u8|flip_f32|gray)<([^>]*)>")
+_POINT = re.compile(r"kr::(?:\(anonymous namespace\)::)?k_(nearest|flip_u8|flip_f32|gray|half)<([^>]*)>")
 
 
 def _short(name: str) -> str:
@@ -65,6 +65,9 @@ def label(name: str) -> str:
         return "generic " + _short(name).split("k_generic")[-1]
     m = _POINT.search(name)
     if m:
+        if m.group(1) == "half":  # <C, DST_F32>: the exact 2x downscale kernel
+            c, f32 = [t.strip() for t in m.group(2).split(",")]
+            return f"resize_{'f32' if f32 == 'true' else 'u8'} c{c} half"
         return f"{m.group(1)}<{m.group(2)}>"
     return _short(name)[:60]
 
@@ -73,6 +76,8 @@ def _point_key(kind: str, args: str) -> str | None:
     a = [t.strip() for t in args.split(",")]
     if kind in ("flip_u8", "flip_f32"):
         return kind if a[0] == "3" else None
+    if kind == "half":  # <C, DST_F32>
+        return None if a[0] != "3" else ("resize_f32" if a[1] == "true" else "resize_u8")
     if kind == "gray":  # <SRC_F32, DST_F32>
         return None if a[0] == "true" else ("gray_f32" if a[1] == "true" else "gray_u8")
     # nearest <C, SRC_F32, DST_F32>; the direction is told apart by grid size

@@ -13,6 +13,7 @@ BATCH_B = "void kr::k_batch<1, 3, false, 4, 8, 1, 1, 3>(kr::TiledJob const*, int
 NEAR = "void kr::(anonymous namespace)::k_nearest<3, false, true>(kr::NearestJob, kr::Epilogue)"
 GRAY = "void kr::(anonymous namespace)::k_gray<false, false>(void const*, void*, int)"
 COPY = "kr::k_copy(unsigned int __vector(4)*, unsigned int __vector(4) const*, unsigned long)"
+HALF = "void kr::(anonymous namespace)::k_half<3, true>(kr::ImageJob, kr::Epilogue)"
 
 
 def test_labels_and_keys():
@@ -26,6 +27,7 @@ def test_labels_and_keys():
     assert profsum.bench_key(BATCH_B) == "batch_warp_u8"
     assert profsum.bench_key(GRAY) == "gray_u8"
     assert profsum.bench_key(NEAR) == "nearest_{}_f32"
+    assert profsum.bench_key(HALF) == "resize_f32" and profsum.label(HALF) == "resize_f32 c3 half"
     assert profsum.bench_key(TILED_W.replace("<1, 3,", "<1, 4,")) is None  # only 3-channel kernels are benchmarked
 
 
