@@ -176,26 +176,31 @@ def test_exact_half_scale(c):
             check_resize(img, h // 2, w // 2, border, 9, what=f"half c={c}")
 
 
-def test_exact_half_scale_views():
-    """The 2x2-mean kernel on crops of a larger buffer (odd pixel offsets)."""
-    par = wl.uniform_u8(300, 500, 3, seed=123)
+@pytest.mark.parametrize("c", [1, 2, 3, 4])
+def test_exact_half_scale_views(c):
+    """The 2x2-mean kernel on crops of a larger buffer (odd pixel offsets, the
+    parent's first and last bytes), u8 and normalised f32 outputs, including
+    rows wider than one wave's 256 outputs (the f32 LDS transpose)."""
+    par = wl.uniform_u8(300, 1100, c, seed=123 + c)
     dev_par = dev(par)
-    for (y, x, h, w) in ((1, 3, 100, 202), (0, 0, 298, 498), (13, 7, 2, 2), (298, 490, 2, 10)):
+    mean, std = (MEAN + (0.5,))[:c], (STD + (0.25,))[:c]
+    for (y, x, h, w) in ((1, 3, 100, 202), (0, 0, 298, 1098), (13, 7, 2, 2), (298, 1090, 2, 10), (5, 1, 40, 1024),
+                         (3, 9, 6, 1040)):
         view = dev_par[y:y + h, x:x + w]
         host = np.ascontiguousarray(par[y:y + h, x:x + w])
         for out in ("u8", "f32"):
-            say(f"half view {y},{x},{h}x{w} {out}")
-            d = torch.empty((h // 2, w // 2, 3), dtype=torch.uint8 if out == "u8" else torch.float32, device="cuda")
+            say(f"half view c={c} {y},{x},{h}x{w} {out}")
+            d = torch.empty((h // 2, w // 2, c), dtype=torch.uint8 if out == "u8" else torch.float32, device="cuda")
             if out == "u8":
                 kr.resize(view, d, border=REPL)
             else:
-                kr.resize(view, d, border=REPL, mean=MEAN, std=STD)
+                kr.resize(view, d, border=REPL, mean=mean, std=std)
             torch.cuda.synchronize()
             if out == "u8":
                 assert_u8_equal(d.cpu().numpy(), oracle.resize(host, h // 2, w // 2, "u8", REPL, threads=TH), "half view")
             else:
-                assert_f32_close(d.cpu().numpy(), oracle.resize(host, h // 2, w // 2, "f64", REPL, 0, MEAN, STD,
-                                                                threads=TH), "half view norm", std=STD)
+                assert_f32_close(d.cpu().numpy(), oracle.resize(host, h // 2, w // 2, "f64", REPL, 0, mean, std,
+                                                                threads=TH), "half view norm", std=std)
 
 
 def test_blank_tiles_match_oracle():
