@@ -7,7 +7,7 @@
 // inside the image, so neither border rule applies.  The general definition
 // then reduces exactly to:
 //   u8:  w0 = w1 = 1024, acc = 2^20 (a + b + c + d), out = (a + b + c + d + 2) >> 2;
-//   f32: the blend with weights 1/2 is exact, v = (a + b + c + d) / 4, then
+//   f32: the blend with 2-D weights 1/4 is exact, v = (a + b + c + d) / 4, then
 //        the epilogue fma(v, alpha_c, beta_c) -- the same bits as the general
 //        kernels.
 // No tap is shared between outputs, so there is nothing to stage: each lane

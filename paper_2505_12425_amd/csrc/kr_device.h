@@ -77,17 +77,25 @@ __device__ __forceinline__ void warp_axis(double s, int n, int &i0, int &w1, flo
     f = (float)fr;
 }
 
-// f32 bilinear blend of four taps with per-axis weights, plus `extra` (the
-// border's share under a CONSTANT border), then the affine epilogue
-// out = v * alpha + beta.  One fixed order of explicit fma so that every
-// kernel computes identical bits.
-__device__ __forceinline__ float blend_f32(float p00, float p01, float p10, float p11, float wx0, float wx1, float wy0,
-                                           float wy1, float extra, float alpha, float beta)
+// f32 bilinear blend of four taps: the 2-D weights w_ij = wy_i * wx_j (one
+// rounded product each, shared by the channels of a pixel), then
+// v = w00 p00 + w01 p01 + w10 p10 + w11 p11 as one fixed chain of explicit
+// fma, so that every kernel computes identical bits.  The caller adds the
+// border's share under a CONSTANT border (adding +-0 to the non-negative sum
+// of u8 taps changes nothing, so paths with and without that add agree) and
+// applies the epilogue out = v * alpha + beta.
+struct Weights2 {
+    float w00, w01, w10, w11;
+};
+
+__device__ __forceinline__ Weights2 weights2(float wx0, float wx1, float wy0, float wy1)
 {
-    const float top = __builtin_fmaf(wx1, p01, wx0 * p00);
-    const float bot = __builtin_fmaf(wx1, p11, wx0 * p10);
-    const float v = __builtin_fmaf(wy1, bot, wy0 * top) + extra;
-    return __builtin_fmaf(v, alpha, beta);
+    return Weights2{wy0 * wx0, wy0 * wx1, wy1 * wx0, wy1 * wx1};
+}
+
+__device__ __forceinline__ float blend4(float p00, float p01, float p10, float p11, const Weights2 &w)
+{
+    return __builtin_fmaf(w.w11, p11, __builtin_fmaf(w.w10, p10, __builtin_fmaf(w.w01, p01, w.w00 * p00)));
 }
 
 // One tap of C channels as integers (u8 source) with the border rule.
@@ -181,6 +189,7 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
         for (int c = 0; c < C; c++)
             dst[c] = (uint8_t)((acc[c] + (1 << 21)) >> 22);
     } else {
+        const Weights2 w = weights2(1.0f - fx, fx, 1.0f - fy, fy);
         float p00[C], p01[C], p10[C], p11[C];
         tap_float<C>(src, j, x0, y0, e, p00);
         tap_float<C>(src, j, x0 + 1, y0, e, p01);
@@ -188,8 +197,7 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
         tap_float<C>(src, j, x0 + 1, y0 + 1, e, p11);
 #pragma unroll
         for (int c = 0; c < C; c++)
-            dst[c] = blend_f32(p00[c], p01[c], p10[c], p11[c], 1.0f - fx, fx, 1.0f - fy, fy, 0.0f, e.alpha[c],
-                               e.beta[c]);
+            dst[c] = __builtin_fmaf(blend4(p00[c], p01[c], p10[c], p11[c], w), e.alpha[c], e.beta[c]);
     }
 }
 

@@ -165,21 +165,26 @@ __device__ __forceinline__ uint32_t mask_weights(int x0, int y0, int W, int H, u
     return (1u << 23) - 4096u * (wy0 + wy1) + 4u * bval * missing;
 }
 
-// f32 interpolation with unquantised weights, then out = v * alpha + beta.
-// The operation order is fixed (explicit fma, no contraction), so every kernel
-// path produces the same bits.
-template <int C>
+// f32 interpolation with unquantised weights (blend4), plus the border's
+// share when EXTRA (CONSTANT border with masked taps), then
+// out = v * alpha + beta.  The operation order is fixed (explicit fma, no
+// contraction), so every kernel path produces the same bits.
+template <int C, bool EXTRA>
 __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t t10, uint32_t t11, float wx0,
                                            float wx1, float wy0, float wy1, float extra, const Epilogue &e,
                                            float (&o)[C])
 {
+    const Weights2 w = weights2(wx0, wx1, wy0, wy1);
 #pragma unroll
     for (int c = 0; c < C; c++) {
         const float p00 = (float)((t00 >> (8 * c)) & 0xFFu);
         const float p01 = (float)((t01 >> (8 * c)) & 0xFFu);
         const float p10 = (float)((t10 >> (8 * c)) & 0xFFu);
         const float p11 = (float)((t11 >> (8 * c)) & 0xFFu);
-        o[c] = blend_f32(p00, p01, p10, p11, wx0, wx1, wy0, wy1, extra, e.alpha[c], e.beta[c]);
+        float v = blend4(p00, p01, p10, p11, w);
+        if constexpr (EXTRA)
+            v = v + extra;
+        o[c] = __builtin_fmaf(v, e.alpha[c], e.beta[c]);
     }
 }
 
@@ -935,8 +940,8 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
                     }
                     const int a = __mul24(y0, pitch) + x0 - base;
-                    interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
-                                  e, o[k]);
+                    interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
+                                        extra, e, o[k]);
                 }
                 store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
             }
@@ -1027,8 +1032,8 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                         wy1 = vy1 ? wy1 : 0.0f;
                         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
                     }
-                    interp_f32<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1, extra,
-                                  e, o[k]);
+                    interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
+                                        extra, e, o[k]);
                 }
                 store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
             }
@@ -1142,7 +1147,7 @@ __device__ __forceinline__ void gather_px_f32(const ImageJob &j, const Epilogue 
         wy1 = (unsigned)(y0 + 1) < (unsigned)H ? wy1 : 0.0f;
         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
     }
-    interp_f32<C>(t00, t01, t10, t11, wx0, wx1, wy0, wy1, extra, e, o);
+    interp_f32<C, true>(t00, t01, t10, t11, wx0, wx1, wy0, wy1, extra, e, o);
 }
 
 template <int OP, int C, bool F32, class L>
