@@ -188,6 +188,31 @@ __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t 
     }
 }
 
+// A wave-uniform value copied into vector registers once.  A vector
+// instruction reads at most one scalar register, so an fma with two uniform
+// operands (alpha and beta of the epilogue, a map coefficient and its offset)
+// would otherwise copy one of them for every pixel; the empty asm pins the
+// copy in a vector register, where the compiler cannot rematerialise it.
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
+// The epilogue with beta in vector registers, for the f32 paths.
+template <int C, bool F32>
+__device__ __forceinline__ Epilogue epilogue_in_vgpr(const Epilogue &e)
+{
+    Epilogue v = e;
+    if constexpr (F32) {
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            v.beta[c] = in_vgpr(e.beta[c]);
+    }
+    return v;
+}
+
 // ------------------------------------------------------------------ stores
 // Lane layout (see compute below): a lane owns PX consecutive pixels of a row.
 // PX = 4: the lane stores 4 pixels at once (12/16 contiguous bytes for u8,
@@ -367,8 +392,10 @@ __device__ __forceinline__ void store_f32_px(float *row, int x, int x_end, const
 {
     if (x >= x_end)
         return;
+    // 32-bit byte offset (a row is far below 4 GiB): with a wave-uniform row
+    // pointer the store takes it as scalar base plus vector offset
+    float *q = reinterpret_cast<float *>(reinterpret_cast<char *>(row) + (uint32_t)x * (uint32_t)(4 * C));
     if constexpr (C == 3) {
-        float *q = row + 3 * (size_t)x;
         if constexpr (NT) {  // three adjacent dwords: one 12-byte store
             put<true>(q, o[0]);
             put<true>(q + 1, o[1]);
@@ -378,7 +405,7 @@ __device__ __forceinline__ void store_f32_px(float *row, int x, int x_end, const
             *reinterpret_cast<F3 *>(q) = F3{o[0], o[1], o[2]};
         }
     } else {
-        put<NT>(reinterpret_cast<f32x4 *>(row + 4 * (size_t)x), f32x4{o[0], o[1], o[2], o[3]});
+        put<NT>(reinterpret_cast<f32x4 *>(q), f32x4{o[0], o[1], o[2], o[3]});
     }
 }
 
@@ -441,7 +468,10 @@ __device__ __forceinline__ void store_row_f32(const ImageJob &j, bool planar, in
                                               const float (&o)[PX][C])
 {
     if (!planar) {
-        store_run_f32<C, PX, NT>(static_cast<float *>(j.dst) + (size_t)y * (size_t)j.dw * C, x, x_end, aligned, o);
+        size_t off = (size_t)y * (size_t)j.dw * C;
+        if constexpr (PX == 1)
+            asm("" : "+s"(off));  // one row per wave: keep its offset scalar, lane offsets 32-bit
+        store_run_f32<C, PX, NT>(static_cast<float *>(j.dst) + off, x, x_end, aligned, o);
         return;
     }
     const size_t plane = (size_t)j.dh * (size_t)j.dw;
@@ -832,6 +862,18 @@ template <int PX_, int TXT_, int CPT_, int RPT_, bool NT_ = false> struct Layout
     __device__ static int row0() { return (int)(threadIdx.x / TXT); }
 };
 
+// Output row y of a lane.  With one-pixel runs a wave covers one row, so y is
+// the same in every lane; reading it from the first lane lets the compiler
+// keep it, and the row's address, in scalar registers.
+template <class L>
+__device__ __forceinline__ int wave_row(int y)
+{
+    if constexpr (L::PX == 1)
+        return __builtin_amdgcn_readfirstlane(y);
+    else
+        return y;
+}
+
 template <int C, bool F32, class L>
 __device__ __forceinline__ bool layout_aligned(int dw)
 {
@@ -854,6 +896,9 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
 #pragma unroll
     for (int i = 0; i < 6; i++)
         m[i] = (F32 || PERSP) ? j.inv[i] : t.m2048[i];
+    m[2] = in_vgpr(m[2]);
+    m[5] = in_vgpr(m[5]);
+    const Epilogue ev = epilogue_in_vgpr<C, F32>(e);
     const int pitch = G.pitch;
     const int base = p.by0 * pitch + p.bx0 - KT_MARGIN;
     const bool aligned = layout_aligned<C, F32, L>(j.dw);
@@ -866,7 +911,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
         for (int k = 0; k < PX; k++)
             xd[c][k] = (double)min(p.ox0 + c * L::SEG + L::col0() + k, p.ox1);
     for (int r = 0; r < L::RPT; r++) {
-        const int y = p.oy0 + L::row0() + r * L::ROWS;
+        const int y = wave_row<L>(p.oy0 + L::row0() + r * L::ROWS);
         if (y > p.oy1)
             break;
         const double rowX = __builtin_fma(m[1], (double)y, m[2]);
@@ -928,9 +973,23 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                             Y = clamp_plain(Y, H);
                         }
                     }
-                    const double fxl = __builtin_floor(X), fyl = __builtin_floor(Y);
-                    const int x0 = (int)fxl, y0 = (int)fyl;
-                    const float fx = (float)(X - fxl), fy = (float)(Y - fyl);
+                    int x0, y0;
+                    float fx, fy;
+                    if constexpr (!CLAMP && !PERSP) {
+                        // inside tiles: X, Y >= 0 at every pixel (the tile's
+                        // extremes sit at its corners), so truncation is the
+                        // floor and fract(X) is X - floor(X), exactly
+                        x0 = (int)X;
+                        y0 = (int)Y;
+                        fx = (float)__builtin_amdgcn_fract(X);
+                        fy = (float)__builtin_amdgcn_fract(Y);
+                    } else {
+                        const double fxl = __builtin_floor(X), fyl = __builtin_floor(Y);
+                        x0 = (int)fxl;
+                        y0 = (int)fyl;
+                        fx = (float)(X - fxl);
+                        fy = (float)(Y - fyl);
+                    }
                     float wx0 = 1.0f - fx, wx1 = fx, wy0 = 1.0f - fy, wy1 = fy, extra = 0.0f;
                     if (MASK) {
                         wx0 = (unsigned)x0 < (unsigned)W ? wx0 : 0.0f;
@@ -941,7 +1000,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                     }
                     const int a = __mul24(y0, pitch) + x0 - base;
                     interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
-                                        extra, e, o[k]);
+                                        extra, ev, o[k]);
                 }
                 store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
             }
@@ -983,8 +1042,9 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
             ca[c][k] = (int)tab[cc];
             cw[c][k] = tab[TW + cc];
         }
+    const Epilogue ev = epilogue_in_vgpr<C, F32>(e);
     for (int r = 0; r < L::RPT; r++) {
-        const int rr = L::row0() + r * L::ROWS;
+        const int rr = wave_row<L>(L::row0() + r * L::ROWS);
         const int y = p.oy0 + rr;
         if (y > p.oy1)
             break;
@@ -1033,7 +1093,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
                     }
                     interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
-                                        extra, e, o[k]);
+                                        extra, ev, o[k]);
                 }
                 store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
             }
@@ -1165,7 +1225,7 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
     for (int i = 0; i < 6; i++)
         m[i] = (F32 || OP == OP_PERSP) ? j.inv[i] : t.m2048[i];
     for (int r = 0; r < L::RPT; r++) {
-        const int rr = L::row0() + r * L::ROWS;
+        const int rr = wave_row<L>(L::row0() + r * L::ROWS);
         const int y = p.oy0 + rr;
         if (y > p.oy1)
             break;
@@ -1269,7 +1329,7 @@ __device__ __forceinline__ void fill_blank(const TiledJob &t, const Plan &p, con
             o[k][c] = __builtin_fmaf(0.0f + e.bval_f, e.alpha[c], e.beta[c]);
     }
     for (int r = 0; r < L::RPT; r++) {
-        const int y = p.oy0 + L::row0() + r * L::ROWS;
+        const int y = wave_row<L>(p.oy0 + L::row0() + r * L::ROWS);
         if (y > p.oy1)
             break;
 #pragma unroll

@@ -27,6 +27,7 @@ TH = 16
 
 def compiled_cfgs(macro):
     text = open(os.path.join(ROOT, "paper_2505_12425_amd", "csrc", "tiled_launch.h")).read()
+    text = text.replace("\\\n", " ")  # join continued macro lines
     body = re.search(rf"#define {macro}\(X\)(.*)", text).group(1)
     return [tuple(int(v) for v in g) for g in re.findall(r"X\((\d+), (\d+), (\d+), (\d+)\)", body)]
 
