@@ -19,7 +19,9 @@ __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, 
 {
     extern __shared__ uint32_t lds[];
     TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT>, MAXIT, PERS>(G, e, lds, [&](TiledJob &t, int &tile) {
+    // f32 outputs leave through non-temporal stores (no kernel of the call
+    // reads them back)
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, PERS>(G, e, lds, [&](TiledJob &t, int &tile) {
         if (!seq.take(tile))
             return false;
         t = job;
