@@ -5,6 +5,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "tiled.h"
 #include "tiled_launch.h"
@@ -45,21 +48,31 @@ int device_cus()
 }
 
 // Resident workgroups per CU for a kernel at a dynamic LDS size, cached per
-// kernel and kilobyte of LDS.
-template <typename K>
-static int blocks_per_cu(K kernel, size_t lds)
+// device, kernel and kilobyte of LDS (the kernels share one signature, so the
+// key holds the kernel's address).
+static int blocks_per_cu(const void *kernel, size_t lds)
 {
-    static int cache[65] = {0};
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, size_t>, int> cache;
     const size_t slot = (lds + 1023) / 1024;
     if (slot > 64)
         return 1;
-    if (cache[slot] == 0) {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, KT_THREADS, slot * 1024) != hipSuccess || n < 1)
-            n = 1;
-        cache[slot] = n;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        dev = -1;
+    const auto key = std::make_tuple(dev, kernel, slot);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const auto it = cache.find(key);
+        if (it != cache.end())
+            return it->second;
     }
-    return cache[slot];
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, KT_THREADS, slot * 1024) != hipSuccess || n < 1)
+        n = 1;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = n;
+    return n;
 }
 
 int persistent_grid(int ntiles, int per_cu)
@@ -271,7 +284,7 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
         return hipSuccess;
     if (persistent) {
         auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, true>;
-        const int grid = persistent_grid(t.ntiles, blocks_per_cu(kern, lds));
+        const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), lds));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
     } else {
         auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, false>;

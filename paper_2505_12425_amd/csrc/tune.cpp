@@ -55,7 +55,7 @@ bool known_cfg(const TuneKey &k, const TileCfg &c)
 }
 
 // Parse the text form (one entry per line, '#' comments).  All or nothing:
-// a malformed line or a configuration this build does not have rejects the
+// a malformed line or a configuration the library was not compiled with rejects the
 // whole text.
 bool parse_table(const std::string &text, std::vector<std::pair<TuneKey, TileCfg>> &out)
 {
