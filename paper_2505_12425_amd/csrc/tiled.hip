@@ -1,6 +1,7 @@
 // tiled.hip -- per-image launches of the LDS-tiled kernels (tiled.h): tile
 // shape, LDS budget and grid for one image.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -34,17 +35,17 @@ __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, 
 
 int device_cus()
 {
-    static int cus[64] = {0};
+    static std::atomic<int> cus[64];  // 0 = not queried yet (static storage starts zeroed)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
         return 256;
-    if (cus[dev] == 0) {
-        int n = 0;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
             n = 256;
-        cus[dev] = n;
+        cus[dev].store(n, std::memory_order_relaxed);
     }
-    return cus[dev];
+    return n;
 }
 
 // Resident workgroups per CU for a kernel at a dynamic LDS size, cached per
