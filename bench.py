@@ -312,6 +312,26 @@ def bench_4k(args, torch, kr, wl):
         kern[n] = {"avg_us": round(ms * 1e3, 3), "launches": reps, "alg_bytes": alg[n], "GBps": round(gbps, 1),
                    "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(px[n] / (ms * 1e-3) / 1e9, 2),
                    "traffic": _traffic_from_profiles(n)}
+    # the traffic-mix ceiling of each kernel: kr_hbm_stream reading one source
+    # copy (the same rotation) and writing that kernel's output buffer, i.e.
+    # the kernel's bytes each way with none of its arithmetic
+    for n in names:
+        for i in range(3):
+            kr.hbm_stream(outs[n], srcs[(k + i) % copies])
+        k += 3
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            kr.hbm_stream(outs[n], srcs[k % copies])
+            k += 1
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        moved = srcs[0].numel() + outs[n].numel() * outs[n].element_size()
+        ceil = moved / (ms * 1e-3) / 1e9
+        kern[n]["mix_ceiling_GBps"] = round(ceil, 1)
+        kern[n]["frac_of_mix_ceiling"] = round(kern[n]["GBps"] / ceil, 4)
     dom = max(names, key=lambda n: kern[n]["avg_us"])
     return {
         "value": px_per_step * args.steps / (total_ms * 1e-3) / 1e9,
@@ -736,7 +756,8 @@ def main():
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": _traffic_from_profiles(dom),
             "alg_bytes_per_launch": k["alg_bytes"], "avg_launch_us": k["avg_us"],
-            "copy_ceiling_GBps": round(copy_like_gbps, 1), "copy_ceiling_1GiB_GBps": round(copy_gbps, 1)}
+            "copy_ceiling_GBps": round(copy_like_gbps, 1), "copy_ceiling_1GiB_GBps": round(copy_gbps, 1),
+            "mix_ceiling_GBps": k["mix_ceiling_GBps"], "frac_of_mix_ceiling": k["frac_of_mix_ceiling"]}
     out = {
         "metric": "output Gpixels/s (4K bilinear resize + warp_affine, u8 and f32 outputs)",
         "value": round(r["value"], 3), "unit": "Gpix/s", "n_gpus": 1, "steps": args.steps,

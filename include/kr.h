@@ -407,6 +407,21 @@ const char *kr_last_error(void);
  */
 kr_status kr_hbm_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/*
+ * Traffic-mix bandwidth probe: reads src_bytes from src and writes dst_bytes
+ * to dst with 16-byte vector loads and stores, so a kernel's HBM traffic (for
+ * example 1 byte read per 4 written, for an RGB u8 -> f32 warp) can be timed
+ * without its arithmetic.  Output chunk i (16 bytes) is the XOR of the input
+ * chunks mapped to it: chunks i*k .. i*k + k - 1 when src_bytes = k *
+ * dst_bytes, chunk i / k when dst_bytes = k * src_bytes, so every input byte is
+ * read and every output byte written once.
+ *   dst, src    device pointers, 16-byte aligned, not overlapping;
+ *   dst_bytes,  multiples of 16, > 0, whose ratio (either way round) is a
+ *   src_bytes   power of two.
+ * Errors: KR_ERR_INVALID_ARGUMENT (nothing launched); KR_ERR_HIP.
+ */
+kr_status kr_hbm_stream(void *dst, size_t dst_bytes, const void *src, size_t src_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -477,4 +477,35 @@ kr_status kr_hbm_copy(void *dst, const void *src, size_t bytes, void *stream)
     return KR_OK;
 }
 
+kr_status kr_hbm_stream(void *dst, size_t dst_bytes, const void *src, size_t src_bytes, void *stream)
+{
+    clear_error();
+    if (!dst || !src)
+        return fail(KR_ERR_INVALID_ARGUMENT, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+        return fail(KR_ERR_INVALID_ARGUMENT, "stream pointers must be 16-byte aligned");
+    if (dst_bytes == 0 || src_bytes == 0 || dst_bytes % 16 || src_bytes % 16)
+        return fail(KR_ERR_INVALID_ARGUMENT, "sizes must be positive multiples of 16");
+    const size_t big = dst_bytes > src_bytes ? dst_bytes : src_bytes;
+    const size_t small = dst_bytes > src_bytes ? src_bytes : dst_bytes;
+    if (big % small)
+        return fail(KR_ERR_INVALID_ARGUMENT, "size ratio is not a power of two");
+    const size_t ratio = big / small;
+    if (ratio & (ratio - 1))
+        return fail(KR_ERR_INVALID_ARGUMENT, "size ratio is not a power of two");
+    int lg = 0;
+    while (((size_t)1 << lg) < ratio)
+        lg++;
+    if (src_bytes > dst_bytes && lg > 8)
+        return fail(KR_ERR_INVALID_ARGUMENT, "at most 256 input chunks per output chunk");
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+    if (s0 < d0 + dst_bytes && d0 < s0 + src_bytes)
+        return fail(KR_ERR_INVALID_ARGUMENT, "stream ranges overlap");
+    const hipError_t err = launch_stream(dst, dst_bytes / 16, src, src_bytes > dst_bytes ? lg : 0,
+                                         dst_bytes > src_bytes ? lg : 0, (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "stream launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
 }  // extern "C"

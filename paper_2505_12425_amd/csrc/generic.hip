@@ -101,4 +101,32 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+// Traffic-mix probe (kr_hbm_stream): one output chunk per thread and step,
+// grid-stride; output chunk i reads input chunks [i << shrink, (i + 1) <<
+// shrink) or input chunk i >> grow.
+__global__ __launch_bounds__(256) void k_stream(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src, size_t n_out,
+                                                int shrink, int grow)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    const int k = 1 << shrink;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n_out; i += stride) {
+        const size_t j = (i << shrink) >> grow;
+        u32x4 v = src[j];
+        for (int q = 1; q < k; q++)
+            v ^= src[j + q];
+        dst[i] = v;
+    }
+}
+
+hipError_t launch_stream(void *dst, size_t n_out, const void *src, int shrink, int grow, hipStream_t s)
+{
+    // enough workgroups to fill the chip several times over, the rest by striding
+    size_t blocks = (n_out + 255) / 256;
+    if (blocks > 256 * 8)
+        blocks = 256 * 8;
+    hipLaunchKernelGGL(k_stream, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4 *)dst, (const u32x4 *)src, n_out,
+                       shrink, grow);
+    return hipGetLastError();
+}
+
 }  // namespace kr

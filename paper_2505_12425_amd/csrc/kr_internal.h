@@ -55,6 +55,10 @@ hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const
 hipError_t launch_persp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
                         hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// Traffic-mix probe: shrink > 0 reads 2^shrink input chunks per output chunk,
+// grow > 0 reads one input chunk for 2^grow output chunks (at most one of them
+// non-zero).
+hipError_t launch_stream(void *dst, size_t n_out, const void *src, int shrink, int grow, hipStream_t s);
 // Flip and RGB -> gray (pointops.hip); the destination is contiguous, sh x sw.
 hipError_t launch_flip(int c, kr_dtype t, const ImageJob &j, int fx, int fy, hipStream_t s);
 hipError_t launch_gray(kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);

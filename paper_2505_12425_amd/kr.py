@@ -101,6 +101,8 @@ def lib():
     L.kr_last_error.restype = ctypes.c_char_p
     L.kr_hbm_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.kr_hbm_copy.restype = i
+    L.kr_hbm_stream.argtypes = [vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp]
+    L.kr_hbm_stream.restype = i
     if hasattr(L, "kr_resize_batch"):
         bip = ctypes.POINTER(BatchItem)
         L.kr_resize_batch_workspace_size.argtypes = [i]
@@ -327,6 +329,14 @@ def hbm_copy(dst, src, nbytes: int | None = None, stream=None) -> None:
     """kr_hbm_copy between two device tensors (the bandwidth ceiling probe)."""
     n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     check(lib().kr_hbm_copy(dst.data_ptr(), src.data_ptr(), n, _stream(stream)))
+
+
+def hbm_stream(dst, src, dst_bytes: int | None = None, src_bytes: int | None = None, stream=None) -> None:
+    """kr_hbm_stream: read src_bytes of src and write dst_bytes of dst (the
+    traffic-mix bandwidth probe); sizes default to the tensors' byte sizes."""
+    nd = dst.numel() * dst.element_size() if dst_bytes is None else int(dst_bytes)
+    ns = src.numel() * src.element_size() if src_bytes is None else int(src_bytes)
+    check(lib().kr_hbm_stream(dst.data_ptr(), nd, src.data_ptr(), ns, _stream(stream)))
 
 
 # ---------------------------------------------------------------- batches

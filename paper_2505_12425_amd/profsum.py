@@ -61,6 +61,8 @@ def label(name: str) -> str:
         return f"{pre}{_OPS[op]}_{dt} c{c} {px}x{txt}x{cpt}x{rpt}"
     if "k_copy" in name:
         return "copy"
+    if "k_stream" in name:
+        return "stream probe"
     if "k_generic" in name:
         return "generic " + _short(name).split("k_generic")[-1]
     m = _POINT.search(name)

@@ -141,6 +141,21 @@ def test_copy_probe_validation():
     assert L.kr_hbm_copy(B, A, 0, None) == kr.OK  # nothing to do, nothing enqueued
 
 
+def test_stream_probe_validation():
+    """kr_hbm_stream rejects, before any launch, what its header rules out."""
+    L = kr.lib()
+    bad = kr.ERR_INVALID_ARGUMENT
+    assert L.kr_hbm_stream(0, 64, A, 16, None) == bad             # NULL
+    assert L.kr_hbm_stream(B, 64, A + 8, 16, None) == bad         # misaligned
+    assert L.kr_hbm_stream(B, 0, A, 16, None) == bad              # empty
+    assert L.kr_hbm_stream(B, 64, A, 24, None) == bad             # not a multiple of 16
+    assert L.kr_hbm_stream(B, 48, A, 16, None) == bad             # ratio 3
+    assert "power of two" in L.kr_last_error().decode()
+    assert L.kr_hbm_stream(B, 16, A, 16 << 9, None) == bad        # 512 input chunks per output chunk
+    assert L.kr_hbm_stream(A + 16, 64, A, 64, None) == bad        # overlap
+    assert "overlap" in L.kr_last_error().decode()
+
+
 def batch_items(n=2, op=0, dst_stride=4096):
     arr = (kr.BatchItem * n)()
     for i in range(n):

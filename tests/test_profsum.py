@@ -21,6 +21,8 @@ def test_labels_and_keys():
     assert profsum.label(TILED_P) == "perspective_u8 c3 4x16x1x4"
     assert profsum.label(BATCH_A) == "batch_warp_u8 c3 4x16x1x2"
     assert profsum.label(COPY) == "copy"
+    assert profsum.label("kr::k_stream(unsigned int __vector(4)*, unsigned int __vector(4) const*, unsigned long, "
+                         "int, int)") == "stream probe"
     assert profsum.label(NEAR) == "nearest<3, false, true>"
     assert profsum.bench_key(TILED_W) == "warp_f32"
     assert profsum.bench_key(TILED_P) == "perspective_u8"
