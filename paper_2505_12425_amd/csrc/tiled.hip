@@ -273,6 +273,9 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
 {
     using L = Layout<PX, TXT, CPT, RPT>;
     constexpr int TW = L::TW, TH = L::TH, MAXIT = 3;
+    // a persistent workgroup holds its next tile's loads in registers while it
+    // interpolates: one group per thread (the rest is staged at commit)
+    constexpr int MAXIT_PERS = 1;
     const TiledJob t = make_tiled_job(j, OP, TW, TH);
     TileGeom G = tile_geom(j, OP, TW, TH);
     if (gather || wants_gather(j, OP)) {
@@ -284,7 +287,7 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
     if (!fits)
         return hipSuccess;
     if (persistent) {
-        auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, true>;
+        auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_PERS, true>;
         const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), lds));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
     } else {
