@@ -414,10 +414,11 @@ kr_status kr_hbm_copy(void *dst, const void *src, size_t bytes, void *stream);
  * without its arithmetic.  Output chunk i (16 bytes) is the XOR of the input
  * chunks mapped to it: chunks i*k .. i*k + k - 1 when src_bytes = k *
  * dst_bytes, chunk i / k when dst_bytes = k * src_bytes, so every input byte is
- * read and every output byte written once.
+ * read (k neighbouring threads share a chunk in the second case) and every
+ * output byte written once.
  *   dst, src    device pointers, 16-byte aligned, not overlapping;
  *   dst_bytes,  multiples of 16, > 0, whose ratio (either way round) is a
- *   src_bytes   power of two.
+ *   src_bytes   power of two, with at most 256 input chunks per output chunk.
  * Errors: KR_ERR_INVALID_ARGUMENT (nothing launched); KR_ERR_HIP.
  */
 kr_status kr_hbm_stream(void *dst, size_t dst_bytes, const void *src, size_t src_bytes, void *stream);
