@@ -331,11 +331,12 @@ static int default_cfgs(int op, bool f32, TileCfg *out)
         out[n++] = TileCfg{a, b, c, d, force_pers ? true : (force_full ? false : pers)};
     };
     // the autotuner's choices on MI355X for 4K sources (3840x2160x3 u8, every
-    // source read from HBM): one workgroup per tile beat persistent grids
+    // source read from HBM): f32 warps run best on a persistent grid of 16-row
+    // columns, u8 warps and resizes with one workgroup per tile
     if (op != OP_RESIZE) {
         if (f32) {
+            add(1, 64, 1, 16, true);
             add(1, 64, 1, 8, false);
-            add(1, 64, 1, 16, false);
         } else {
             add(4, 16, 1, 4, false);
             add(4, 16, 1, 2, false);
