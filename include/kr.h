@@ -259,6 +259,32 @@ kr_status kr_resize_batch_ex(const kr_batch_item *items, int n, int c, kr_dtype 
                              void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * kr_resize_batch_ex for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same validation, kernels and outputs (bit-identical to
+ * kr_resize_batch_ex on the same items), with the work-list written to a
+ * device scratch array of the library's own instead of a caller workspace.
+ *  - The scratch is KR_NOALLOC_SCRATCH_BYTES (1 MiB) per GPU, held from the
+ *    library's load until the process ends; a batch may have at most
+ *    KR_NOALLOC_MAX_ITEMS items (KR_ERR_WORKSPACE_TOO_SMALL beyond that,
+ *    nothing enqueued).
+ *  - The call allocates no device memory (no hipMalloc, hipFree or
+ *    allocating library routine); it uploads the work-list with one
+ *    hipMemcpyAsync from host memory on stream, then launches.
+ *  - Every call on one GPU shares that GPU's scratch, which keeps the last
+ *    call's work-list: calls on one GPU must be ordered (issued on one stream,
+ *    or synchronised); calls that overlap on one GPU race and may read each
+ *    other's work-lists.
+ *  - The scratch of a device is looked up (hipGetSymbolAddress) on the first
+ *    call with that device current; KR_ERR_HIP if that fails.
+ */
+#define KR_NOALLOC_SCRATCH_BYTES (1u << 20)
+#define KR_NOALLOC_MAX_ITEMS 4096
+kr_status kr_resize_batch_noalloc(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                                  kr_border border, float border_value, const kr_normalize *norm, int dst_layout,
+                                  void *stream);
+
+/*
  * A reusable batch: kr_batch_plan_create validates the items, builds the
  * work-list once (it allocates and fills its own device memory, synchronously)
  * and captures the batch's launches into a HIP graph (kernel nodes only).

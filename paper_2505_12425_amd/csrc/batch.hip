@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <new>
 #include <vector>
@@ -289,6 +290,49 @@ static kr_status check_items(const kr_batch_item *items, int n, int c, kr_dtype 
 // each 256-byte aligned (at most KB_MAX_GROUPS groups over n items).
 size_t kr::table_bytes(int n) { return ((size_t)n * sizeof(TiledJob) + 255) & ~(size_t)255; }
 
+// Validate a batch, write its work-list into the device buffer table (of
+// table_bytes bytes) on stream and enqueue its launches.
+static kr_status enqueue_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
+                               kr_border border, float border_value, const kr_normalize *norm, int dst_layout,
+                               void *table, size_t table_bytes, hipStream_t s)
+{
+    if (dst_layout != KR_LAYOUT_HWC && dst_layout != KR_LAYOUT_CHW)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown destination layout %d", dst_layout);
+    std::vector<ImageJob> rs, ws;
+    kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, rs, ws);
+    if (st != KR_OK)
+        return st;
+    if (n == 0)
+        return KR_OK;
+    if (!tiled_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+    if (!table || reinterpret_cast<uintptr_t>(table) % 256 != 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+    if (table_bytes < kr_resize_batch_workspace_size(n))
+        return fail(KR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", table_bytes,
+                    kr_resize_batch_workspace_size(n));
+    Epilogue e = make_epilogue(c, border, border_value, norm);
+    e.planar = dst_layout == KR_LAYOUT_CHW;
+    const bool f32 = dst_t == KR_F32;
+    const std::vector<ImageJob> imgs[2] = {rs, ws};
+    const TileCfg *const none[2] = {nullptr, nullptr};
+    BatchBuild bb;
+    build_batch(imgs, f32, c, none, bb);
+    std::vector<uint8_t> host(bb.bytes());
+    bb.pack(host.data());
+    // pageable source: the runtime stages it before the call returns
+    hipError_t err = hipMemcpyAsync(table, host.data(), host.size(), hipMemcpyHostToDevice, s);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "work-list upload failed: %s", hipGetErrorString(err));
+    bb.bind(table);
+    for (const BatchGroup &g : bb.groups) {
+        err = launch_group(g, c, dst_t, e, s);
+        if (err != hipSuccess)
+            return fail(KR_ERR_HIP, "batch launch failed: %s", hipGetErrorString(err));
+    }
+    return KR_OK;
+}
+
 extern "C" {
 
 size_t kr_resize_batch_workspace_size(int n) { return n > 0 ? table_bytes(n) + KB_MAX_GROUPS * 256 : 256; }
@@ -306,45 +350,76 @@ kr_status kr_resize_batch_ex(const kr_batch_item *items, int n, int c, kr_dtype 
                              void *workspace, size_t workspace_bytes, void *stream)
 {
     clear_error();
-    if (dst_layout != KR_LAYOUT_HWC && dst_layout != KR_LAYOUT_CHW)
-        return fail(KR_ERR_INVALID_ARGUMENT, "unknown destination layout %d", dst_layout);
-    std::vector<ImageJob> rs, ws;
-    kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, rs, ws);
-    if (st != KR_OK)
-        return st;
-    if (n == 0)
-        return KR_OK;
-    if (!tiled_supported(c, src_t))
-        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
-    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-        return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
-    if (workspace_bytes < kr_resize_batch_workspace_size(n))
-        return fail(KR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", workspace_bytes,
-                    kr_resize_batch_workspace_size(n));
-    Epilogue e = make_epilogue(c, border, border_value, norm);
-    e.planar = dst_layout == KR_LAYOUT_CHW;
-    hipStream_t s = (hipStream_t)stream;
-    const bool f32 = dst_t == KR_F32;
-    const std::vector<ImageJob> imgs[2] = {rs, ws};
-    const TileCfg *const none[2] = {nullptr, nullptr};
-    BatchBuild bb;
-    build_batch(imgs, f32, c, none, bb);
-    std::vector<uint8_t> host(bb.bytes());
-    bb.pack(host.data());
-    // pageable source: the runtime stages it before the call returns
-    hipError_t err = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, s);
-    if (err != hipSuccess)
-        return fail(KR_ERR_HIP, "work-list upload failed: %s", hipGetErrorString(err));
-    bb.bind(workspace);
-    for (const BatchGroup &g : bb.groups) {
-        err = launch_group(g, c, dst_t, e, s);
-        if (err != hipSuccess)
-            return fail(KR_ERR_HIP, "batch launch failed: %s", hipGetErrorString(err));
-    }
-    return KR_OK;
+    return enqueue_batch(items, n, c, src_t, dst_t, border, border_value, norm, dst_layout, workspace,
+                         workspace_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free form
+// The batch entry point for callers that cannot allocate: its work-list goes
+// to a device array of the library's own instead of a caller workspace.
+// Each GPU holds its own copy of the array from the library's load until the
+// process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in, not a device address).
+namespace {
+
+constexpr size_t KB_SCRATCH_BYTES = size_t(1) << 20;
+static_assert(KB_SCRATCH_BYTES == KR_NOALLOC_SCRATCH_BYTES, "kr.h states the scratch size");
+static_assert(KR_NOALLOC_MAX_ITEMS * sizeof(TiledJob) + 255 + KB_MAX_GROUPS * 256 <= KB_SCRATCH_BYTES,
+              "the largest allocation-free batch's work-list fits the scratch");
+
+static __device__ __align__(256) uint8_t scratch[KB_SCRATCH_BYTES];
+
+constexpr int KB_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[KB_MAX_DEVICES];  // per device, set once with that device current
+
+// The current device's address of scratch, looked up on the first call on
+// that device.
+hipError_t scratch_on_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return err;
+    if (dev < 0 || dev >= KB_MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess)
+            return err;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" kr_status kr_resize_batch_noalloc(const kr_batch_item *items, int n, int c, kr_dtype src_t,
+                                             kr_dtype dst_t, kr_border border, float border_value,
+                                             const kr_normalize *norm, int dst_layout, void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return fail(KR_ERR_INVALID_ARGUMENT, "item count %d out of range", n);
+    if (n > KR_NOALLOC_MAX_ITEMS)
+        return fail(KR_ERR_WORKSPACE_TOO_SMALL,
+                    "%d items: the allocation-free entry point takes at most %d (its work-list lives in a "
+                    "%zu-byte device scratch)", n, KR_NOALLOC_MAX_ITEMS, KB_SCRATCH_BYTES);
+    void *ws = nullptr;
+    const hipError_t err = scratch_on_current_device(&ws);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "device scratch lookup failed: %s", hipGetErrorString(err));
+    return enqueue_batch(items, n, c, src_t, dst_t, border, border_value, norm, dst_layout, ws, KB_SCRATCH_BYTES,
+                         (hipStream_t)stream);
+}
 
 // ------------------------------------------------------------------ plans
 struct kr_batch_plan {

@@ -33,6 +33,7 @@ OP_RESIZE = 0
 OP_WARP = 1
 LAYOUT_HWC = 0
 LAYOUT_CHW = 1
+NOALLOC_MAX_ITEMS = 4096  # kr.h KR_NOALLOC_MAX_ITEMS
 
 
 class KrError(RuntimeError):
@@ -113,6 +114,8 @@ def lib():
         L.kr_batch_plan_create.restype = i
         L.kr_resize_batch_ex.argtypes = [bip, i, i, i, i, i, f, npp, i, vp, ctypes.c_size_t, vp]
         L.kr_resize_batch_ex.restype = i
+        L.kr_resize_batch_noalloc.argtypes = [bip, i, i, i, i, i, f, npp, i, vp]
+        L.kr_resize_batch_noalloc.restype = i
         L.kr_batch_plan_create_ex.argtypes = [bip, i, i, i, i, i, f, npp, i, ctypes.POINTER(vp)]
         L.kr_batch_plan_create_ex.restype = i
         L.kr_batch_plan_launch.argtypes = [vp, vp]
@@ -397,6 +400,18 @@ def resize_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean
     check(lib().kr_resize_batch_ex(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
                                    int(layout), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                                    _stream(stream)))
+
+
+def resize_batch_noalloc(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
+                         stream=None, layout: int = LAYOUT_HWC) -> None:
+    """kr_resize_batch_noalloc: resize_batch with the work-list in the
+    library's own device scratch (nothing is allocated; at most
+    NOALLOC_MAX_ITEMS items; calls on one GPU must be ordered)."""
+    arr, n, c, st, dt = _batch_items(specs, layout)
+    if n == 0:
+        return
+    check(lib().kr_resize_batch_noalloc(arr, n, c, st, dt, border, float(border_value), _normalize(mean, std, c),
+                                        int(layout), _stream(stream)))
 
 
 # ---------------------------------------------------------------- autotuning
