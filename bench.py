@@ -348,6 +348,23 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, np.float64), q))
 
 
+def _graph_of(torch, fn):
+    """fn's launches captured once into a HIP graph (through torch's graph
+    capture on its current stream): the per-image baseline without the
+    Python and host-call cost of each launch."""
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()  # warm: one-time host work (occupancy queries) stays out of the capture
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    return g
+
+
 def _time_loop(torch, fn, reps):
     """Per-call durations (ms) of fn() with an event pair around each call."""
     out = []
@@ -386,15 +403,18 @@ def bench_batch(args, torch, kr, wl):
     def batched():
         kr.resize_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws)
 
-    for f in (per_image, batched, plan.launch):
+    g_img = _graph_of(torch, per_image)
+    for f in (per_image, batched, plan.launch, g_img.replay):
         for _ in range(args.warmup):
             f()
     torch.cuda.synchronize()
-    reps = max(args.steps, 200)
+    reps = max(args.steps, 200) if not args.systems_lite else 100
     t_img = _time_loop(torch, per_image, max(args.steps, 20))
+    t_img_g = _time_loop(torch, g_img.replay, reps)
     t_bat = _time_loop(torch, batched, reps)
     t_plan = _time_loop(torch, plan.launch, reps)
     plan.close()
+    del g_img
     # the same batch into planar CHW destinations (one NCHW tensor, model-ready)
     nchw = torch.empty((len(shapes), 3, 224, 224), dtype=torch.float32, device="cuda")
     specs_chw = [{"op": "resize", "src": s, "dst": nchw[i]} for i, s in enumerate(srcs)]
@@ -419,9 +439,12 @@ def bench_batch(args, torch, kr, wl):
                      "traffic": _traffic_from_profiles("batch_resize_f32"), "alg_bytes_per_launch": alg,
                      "avg_launch_us": round(ms * 1e3, 3)},
         "per_image_ms": round(float(np.median(t_img)), 4), "batched_ms": round(float(np.median(t_bat)), 4),
+        "per_image_graph_ms": round(float(np.median(t_img_g)), 4),
         "plan_ms": round(ms, 4), "speedup_vs_per_image": round(float(np.median(t_img)) / ms, 2),
+        "speedup_vs_per_image_graph": round(float(np.median(t_img_g)) / ms, 2),
         "plan_p50_ms": round(_pct(t_plan, 50), 4), "plan_p99_ms": round(_pct(t_plan, 99), 4),
-        "per_image_p99_ms": round(_pct(t_img, 99), 4), "autotune": tuned,
+        "per_image_p99_ms": round(_pct(t_img, 99), 4), "per_image_graph_p99_ms": round(_pct(t_img_g, 99), 4),
+        "autotune": tuned,
         "plan_nchw_ms": round(float(np.median(t_chw)), 4), "plan_nchw_p99_ms": round(_pct(t_chw, 99), 4),
     }
 
@@ -448,13 +471,17 @@ def bench_warpbatch(args, torch, kr, wl):
         for s, d, m in zip(srcs, dsts, mats):
             kr.warp_affine(s, d, m, border=kr.CONSTANT)
 
-    for f in (per_image, plan.launch):
+    g_img = _graph_of(torch, per_image)
+    for f in (per_image, plan.launch, g_img.replay):
         for _ in range(args.warmup):
             f()
     torch.cuda.synchronize()
+    reps = max(args.steps, 200) if not args.systems_lite else 100
     t_img = _time_loop(torch, per_image, max(args.steps, 20))
-    t_plan = _time_loop(torch, plan.launch, max(args.steps, 200))
+    t_img_g = _time_loop(torch, g_img.replay, reps)
+    t_plan = _time_loop(torch, plan.launch, reps)
     plan.close()
+    del g_img
     touched = sum(warp_touched_bytes(1080, 1920, 1080, 1920, kr.invert_affine(m.reshape(6))) for m in mats)
     alg = touched + 64 * 1080 * 1920 * 3
     px = 64 * 1080 * 1920
@@ -471,8 +498,11 @@ def bench_warpbatch(args, torch, kr, wl):
                      "traffic": _traffic_from_profiles("batch_warp_u8"), "alg_bytes_per_launch": alg,
                      "avg_launch_us": round(ms * 1e3, 3)},
         "per_image_ms": round(float(np.median(t_img)), 4), "plan_ms": round(ms, 4),
+        "per_image_graph_ms": round(float(np.median(t_img_g)), 4),
         "speedup_vs_per_image": round(float(np.median(t_img)) / ms, 2),
+        "speedup_vs_per_image_graph": round(float(np.median(t_img_g)) / ms, 2),
         "plan_p50_ms": round(_pct(t_plan, 50), 4), "plan_p99_ms": round(_pct(t_plan, 99), 4),
+        "per_image_graph_p99_ms": round(_pct(t_img_g, 99), 4),
         "autotune": tuned,
     }
 
@@ -663,15 +693,17 @@ def bench_serve(args, torch, kr, wl):
     sat = run(0, 4, 64, budget)
     sat_fifo = run(0, 1, 1, budget)
     sweep = []
-    for frac in (0.25, 0.5, 0.75, 0.9):
+    for frac in ((0.9,) if args.systems_lite else (0.25, 0.5, 0.75, 0.9)):
         q = frac * sat["req_s"]
         sweep.append({"frac_of_saturation": frac, "batched": run(q, 4, 64, budget), "fifo": run(q, 1, 1, budget)})
     head = max((s for s in sweep if s["batched"]["p99_ms"] <= args.slo_ms), key=lambda s: s["frac_of_saturation"],
                default=sweep[0])
     # a 64 MiB output arena forces requests to queue for memory
     stress_budget = 64 << 20
-    stress = {"budget_mb": 64, "saturation": run(0, 4, 64, stress_budget),
-              "at_0.5_of_saturation": run(0.5 * sat["req_s"], 4, 64, stress_budget)}
+    stress = None
+    if not args.systems_lite:
+        stress = {"budget_mb": 64, "saturation": run(0, 4, 64, stress_budget),
+                  "at_0.5_of_saturation": run(0.5 * sat["req_s"], 4, 64, stress_budget)}
     return {
         "metric": "served output Gpixels/s at the highest swept QPS meeting the p99 SLO (continuous batching)",
         "value": head["batched"]["Gpix_s"], "unit": "Gpix/s", "ms_per_step": None,
@@ -683,6 +715,36 @@ def bench_serve(args, torch, kr, wl):
                        "speedup_vs_fifo": round(sat["req_s"] / max(sat_fifo["req_s"], 1e-9), 2)},
         "sweep": sweep, "headline": head, "stress_64MiB": stress,
     }
+
+
+def bench_systems(args, torch, kr, wl):
+    """The batched and served forms next to per-image launches, bounded for
+    the default run: the 256-image resize batch and the 64-warp batch (graph
+    plan vs per-image launches, eager and graph-captured) and a served trace
+    of args.systems_requests requests at saturation and at 0.9x of it."""
+    lite = argparse.Namespace(**vars(args))
+    lite.systems_lite = True
+    lite.warmup = 3
+    lite.steps = 20
+    lite.requests = args.systems_requests
+    out = {}
+    b = bench_batch(lite, torch, kr, wl)
+    out["batch_resize_256"] = {k: b[k] for k in (
+        "value", "unit", "plan_ms", "plan_p50_ms", "plan_p99_ms", "per_image_ms", "per_image_graph_ms",
+        "per_image_graph_p99_ms", "speedup_vs_per_image", "speedup_vs_per_image_graph", "plan_nchw_ms")}
+    out["batch_resize_256"]["roofline_frac"] = b["roofline"]["frac"]
+    w = bench_warpbatch(lite, torch, kr, wl)
+    out["batch_warp_64x1080p"] = {k: w[k] for k in (
+        "value", "unit", "plan_ms", "plan_p50_ms", "plan_p99_ms", "per_image_ms", "per_image_graph_ms",
+        "per_image_graph_p99_ms", "speedup_vs_per_image", "speedup_vs_per_image_graph")}
+    out["batch_warp_64x1080p"]["roofline_frac"] = w["roofline"]["frac"]
+    torch.cuda.empty_cache()
+    sv = bench_serve(lite, torch, kr, wl)
+    h = sv["sweep"][0]
+    out["served"] = {"requests": lite.requests, "saturation": sv["saturation"],
+                     "at_0.9_of_saturation": {"batched": h["batched"], "fifo": h["fifo"]},
+                     "p99_speedup_vs_fifo_at_0.9": round(h["fifo"]["p99_ms"] / max(h["batched"]["p99_ms"], 1e-9), 2)}
+    return out
 
 
 def _save_tuning(args, kr):
@@ -698,6 +760,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve", "ops", "warpseeds"])
     ap.add_argument("--cold-copies", type=int, default=16)
+    ap.add_argument("--no-systems", action="store_true",
+                    help="4k workload: skip the batched/served sub-records")
+    ap.add_argument("--systems-requests", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "file", "live", "off"],
                     help="tile configurations: file = load --tune-file (the table the tuner wrote on MI355X), "
@@ -722,11 +787,21 @@ def main():
     kr.lib()
     args.tune_mode = args.tune if args.tune != "auto" else ("file" if os.path.exists(args.tune_file) else "live")
     kr.autotune_clear()
+    stale = None
     if args.tune_mode == "file":
-        kr.autotune_load(open(args.tune_file).read())
-    tuning = {"mode": args.tune_mode}
+        try:
+            kr.autotune_load(open(args.tune_file).read())
+        except kr.KrError as e:
+            # a table measured on other kernel sources (or another GPU) no
+            # longer names the fastest configurations: re-tune (auto) or fail
+            if args.tune != "auto" or e.status != kr.ERR_UNSUPPORTED:
+                raise
+            stale, args.tune_mode = str(e), "live"
+    tuning = {"mode": args.tune_mode, "build_key": kr.build_key()}
     if args.tune_mode == "file":
         tuning["file"] = os.path.relpath(args.tune_file, ROOT)
+    if stale:
+        tuning["stale_file"] = stale
     common = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     # the copy ceilings (the 1 GiB one is also the calibration point of HBM byte counters)
@@ -766,6 +841,10 @@ def main():
         "config": r["config"], "roofline": roof, "kernels": r["kernels"],
         "tuning": dict(tuning, reports=r["autotune"]),
     }
+    if not args.no_systems:
+        del r["cpu_args"][0:0]
+        torch.cuda.empty_cache()
+        out["systems"] = bench_systems(args, torch, kr, wl)
     _save_tuning(args, kr)
     if not args.no_cpu_baseline:
         img, m = r["cpu_args"]

@@ -205,6 +205,27 @@ kr_status kr_flip_view(const void *src, int h, int w, size_t src_pitch, int c, k
 kr_status kr_rgb_to_gray_view(const void *src, int h, int w, size_t src_pitch, kr_dtype src_t,
                               void *dst, kr_dtype dst_t, const kr_normalize *norm, void *stream);
 
+/*
+ * Resize / affine warp fused with RGB -> gray (ITU-R BT.601 luma): the
+ * source is an RGB u8 image (src_pitch bytes between rows, 0 = contiguous;
+ * the rules of kr_resize_bilinear_view), dst one channel of dst_h x dst_w,
+ * u8 or f32 (KR_ERR_UNSUPPORTED otherwise).  The result equals the operator
+ * (kr_resize_bilinear / kr_warp_affine with u8 source and dst_t output,
+ * without normalisation) followed by kr_rgb_to_gray, bit for bit, in one
+ * pass: u8 interpolates each channel to u8 (11-bit weights), then takes the
+ * 14-bit gray weights with their rounding; f32 combines the 0..255 channel
+ * values in binary32.  norm (f32 only) normalises the gray with mean[0] and
+ * std[0]; border_value is a u8 sample in [0, 255] for either output type.
+ * The paper benchmarks resizing and RGB -> gray as operators (Sec. III) and
+ * converts captured frames to gray (Sec. IV-B).
+ */
+kr_status kr_resize_bilinear_gray(const void *src, int src_h, int src_w, size_t src_pitch, void *dst, int dst_h,
+                                  int dst_w, kr_dtype dst_t, kr_border border, float border_value,
+                                  const kr_normalize *norm, void *stream);
+kr_status kr_warp_affine_gray(const void *src, int src_h, int src_w, size_t src_pitch, void *dst, int dst_h,
+                              int dst_w, kr_dtype dst_t, const double m[6], int flags, kr_border border,
+                              float border_value, const kr_normalize *norm, void *stream);
+
 /* One image of a batch.  op: 0 = resize, 1 = warp.  m and flags are read for
  * warps only (same meaning as in kr_warp_affine).  src_pitch: bytes between
  * source rows, 0 for a contiguous source, else a view with the rules of
@@ -288,10 +309,12 @@ kr_status kr_resize_batch_noalloc(const kr_batch_item *items, int n, int c, kr_d
  * A reusable batch: kr_batch_plan_create validates the items, builds the
  * work-list once (it allocates and fills its own device memory, synchronously)
  * and captures the batch's launches into a HIP graph (kernel nodes only).
- * kr_batch_plan_launch replays that graph on stream.  Source and destination
- * buffers named by the items must stay valid while the plan is used.
- * kr_batch_plan_destroy frees the plan (after synchronising its last launch);
- * NULL is ignored.
+ * kr_batch_plan_launch replays that graph on stream.  Replays of one plan are
+ * ordered: a replay on another stream starts after the previous replay has
+ * completed.  Source and destination buffers named by the items must stay
+ * valid while the plan is used.
+ * kr_batch_plan_destroy waits for the plan's own replays (no other work of
+ * the device) and frees it; NULL is ignored.
  */
 typedef struct kr_batch_plan kr_batch_plan;
 kr_status kr_batch_plan_create(const kr_batch_item *items, int n, int c, kr_dtype src_t,
@@ -403,9 +426,16 @@ void kr_server_destroy(kr_server *server);
  * report; tunes the resize and the warp launch of the batch separately.
  * kr_autotune_save: writes the table as text into buf (truncated to len
  * bytes, NUL-terminated) and returns the bytes the full text needs.
- * kr_autotune_load: merges a text table (as written by kr_autotune_save);
- * a malformed line or an unknown configuration rejects the whole text
- * (KR_ERR_INVALID_ARGUMENT, table unchanged).
+ * kr_autotune_load: merges a text table (as written by kr_autotune_save).
+ * Its first entry line is "key <arch> <hash>", the build key of the library
+ * that measured it (kr_build_key); a table with another key is stale
+ * (another GPU architecture, or kernels edited since) and is ignored
+ * (KR_ERR_UNSUPPORTED, table unchanged).  A missing key, a malformed line or
+ * an unknown configuration rejects the whole text (KR_ERR_INVALID_ARGUMENT,
+ * table unchanged).  The KR_AUTOTUNE_CACHE file follows the same rules (a
+ * rejected file is reported on stderr and ignored).
+ * kr_build_key: "<arch> <hash>", static text: the GPU architecture the
+ * library was compiled for and a hash of its kernel sources.
  * kr_autotune_clear: empties the table (launches return to the defaults).
  */
 kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c, kr_dtype src_t, void *dst,
@@ -418,6 +448,7 @@ kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c, kr_dtype s
                             char *report, size_t report_len);
 size_t kr_autotune_save(char *buf, size_t len);
 kr_status kr_autotune_load(const char *text);
+const char *kr_build_key(void);
 void kr_autotune_clear(void);
 
 /* Static text for a status code. */

@@ -183,6 +183,41 @@ def warp(src: np.ndarray, m6, dh: int, dw: int, out: str = "u8", inverse: bool =
     return dst
 
 
+def resize_gray(src: np.ndarray, dh: int, dw: int, out: str = "u8", border: int = REPLICATE,
+                bval: float = 0.0, mean=None, std=None, threads: int = 1) -> np.ndarray:
+    """Bilinear resize of an RGB image to one BT.601 gray channel, the
+    resize followed by the RGB -> gray operator (paper Sec. III benchmarks
+    both; the camera-stream listing of Sec. IV-B converts a captured frame
+    to gray).  Reading: the fused form computes exactly that composition.
+    u8: each channel interpolated and rounded to u8 (11-bit weights), then
+    the 14-bit gray weights and their own rounding; f64: the unnormalised
+    channel values, the gray combination, then (v / 255 - mean) / std with
+    mean[0], std[0].  HxWx3 -> dh x dw x 1."""
+    if out == "u8":
+        return rgb_to_gray(resize(src, dh, dw, "u8", border, bval, threads=threads), "u8", threads=threads)
+    return _gray_f64(resize(src, dh, dw, "f64", border, bval, threads=threads), mean, std)
+
+
+def warp_gray(src: np.ndarray, m6, dh: int, dw: int, out: str = "u8", inverse: bool = False,
+              border: int = CONSTANT, bval: float = 0.0, mean=None, std=None, threads: int = 1) -> np.ndarray:
+    """Affine warp of an RGB image to one BT.601 gray channel: the warp
+    followed by the RGB -> gray operator, with the same reading as
+    resize_gray (u8: per-channel rounding, then the gray rounding)."""
+    if out == "u8":
+        return rgb_to_gray(warp(src, m6, dh, dw, "u8", inverse, border, bval, threads=threads), "u8",
+                           threads=threads)
+    return _gray_f64(warp(src, m6, dh, dw, "f64", inverse, border, bval, threads=threads), mean, std)
+
+
+def _gray_f64(v: np.ndarray, mean, std) -> np.ndarray:
+    """BT.601 luma of binary64 RGB values, in the order kro_rgb_to_gray uses
+    (0.299 R + 0.587 G + 0.114 B), then the optional normalisation."""
+    g = 0.299 * v[..., 0] + 0.587 * v[..., 1] + 0.114 * v[..., 2]
+    if mean is not None:
+        g = (g / 255.0 - float(list(mean)[0])) / float(list(std)[0])
+    return g[..., None]
+
+
 def invert_affine(m6) -> np.ndarray:
     """Inverse of a 2x3 affine map by the fixed formula in kro.c."""
     lib = _load()

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -27,11 +28,25 @@ COMMON = ["-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(RO
           "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
 
+def source_sha() -> str:
+    """Hash of every kernel and host source file of libkr (the build key of
+    its tuning tables)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if src.endswith(".cpp"):
         # host ABI code: products and sums must round exactly as written
         cmd = ["hipcc", "-O2", "-ffp-contract=off"] + COMMON + ["-c", src, "-o", obj]
+        if os.path.basename(src) == "tune.cpp":
+            cmd.insert(-4, f'-DKR_SOURCE_SHA="{source_sha()}"')
     else:
         cmd = ["hipcc", "-O3"] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -120,9 +120,11 @@ kr_status check_common(const void *src, int sh, int sw, int c, kr_dtype st, void
                 return fail(KR_ERR_INVALID_ARGUMENT, "normalisation channel %d has a bad mean/std", i);
     }
     const uintptr_t s0 = reinterpret_cast<uintptr_t>(src);
-    const uintptr_t s1 = s0 + source_span(sh, sw, c, st, src_pitch);
+    const uintptr_t s1 = range_end(src, source_span(sh, sw, c, st, src_pitch));
     const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst);
-    const uintptr_t d1 = d0 + (uintptr_t)dh * (uintptr_t)dw * (uintptr_t)c * elem_size(dt);
+    const uintptr_t d1 = range_end(dst, (size_t)dh * (size_t)dw * (size_t)c * elem_size(dt));
+    if (!s1 || !d1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src or dst range wraps past the end of the address space");
     if (s0 < d1 && d0 < s1)
         return fail(KR_ERR_INVALID_ARGUMENT, "src and dst overlap");
     return KR_OK;
@@ -146,6 +148,55 @@ Epilogue make_epilogue(int c, kr_border border, float bval, const kr_normalize *
     e.bval_f = bval;
     e.bval_i = (int)bval;
     e.border = (int)border;
+    return e;
+}
+
+// The fused gray forms: RGB u8 source (a view when src_pitch != 0), one
+// channel out (u8 or f32); the u8 rules for the border value; norm (f32 only)
+// normalises the gray with mean[0], std[0].
+static kr_status check_gray(const void *src, int sh, int sw, size_t src_pitch, void *dst, int dh, int dw,
+                            kr_dtype dt, kr_border border, float bval, const kr_normalize *norm)
+{
+    if (dt != KR_U8 && dt != KR_F32)
+        return fail(KR_ERR_UNSUPPORTED, "dtype pair (0 -> %d) not supported", (int)dt);
+    if (border != KR_BORDER_CONSTANT && border != KR_BORDER_REPLICATE)
+        return fail(KR_ERR_UNSUPPORTED, "border mode %d not supported", (int)border);
+    kr_status s = check_source(src, sh, sw, 3, KR_U8, src_pitch);
+    if (s == KR_OK)
+        s = check_image("dst", dst, dh, dw, 1);
+    if (s != KR_OK)
+        return s;
+    if (!std::isfinite(bval) || bval < 0.0f || bval > 255.0f || bval != std::floor(bval))
+        return fail(KR_ERR_INVALID_ARGUMENT, "u8 border value %g is not an integer in [0, 255]", (double)bval);
+    if (norm) {
+        if (dt != KR_F32)
+            return fail(KR_ERR_INVALID_ARGUMENT, "normalisation needs an f32 destination");
+        if (!std::isfinite(norm->mean[0]) || !std::isfinite(norm->std[0]) || norm->std[0] == 0.0f)
+            return fail(KR_ERR_INVALID_ARGUMENT, "normalisation has a bad mean/std");
+    }
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+    const uintptr_t s1 = range_end(src, source_span(sh, sw, 3, KR_U8, src_pitch));
+    const uintptr_t d1 = range_end(dst, (size_t)dh * (size_t)dw * elem_size(dt));
+    if (!s1 || !d1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src or dst range wraps past the end of the address space");
+    if (s0 < d1 && d0 < s1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src and dst overlap");
+    return KR_OK;
+}
+
+// Channels unnormalised (the gray combines the 0..255 values), the gray then
+// normalised with mean[0], std[0] like the standalone RGB -> gray operator.
+static Epilogue make_gray_epilogue(kr_border border, float bval, const kr_normalize *norm)
+{
+    Epilogue e = make_epilogue(3, border, bval, nullptr);
+    e.gray = 1;
+    e.galpha = 1.0f;
+    e.gbeta = 0.0f;
+    if (norm) {
+        const double sd = (double)norm->std[0];
+        e.galpha = (float)(1.0 / (255.0 * sd));
+        e.gbeta = (float)(-(double)norm->mean[0] / sd);
+    }
     return e;
 }
 
@@ -256,6 +307,50 @@ kr_status kr_warp_affine(const void *src, int src_h, int src_w, int c, kr_dtype 
                                border_value, norm, stream);
 }
 
+kr_status kr_resize_bilinear_gray(const void *src, int src_h, int src_w, size_t src_pitch, void *dst, int dst_h,
+                                  int dst_w, kr_dtype dst_t, kr_border border, float border_value,
+                                  const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    const kr_status s = check_gray(src, src_h, src_w, src_pitch, dst, dst_h, dst_w, dst_t, border, border_value,
+                                   norm);
+    if (s != KR_OK)
+        return s;
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    set_source(j, src, src_h, src_w, 3, KR_U8, src_pitch);
+    j.dst = dst; j.dh = dst_h; j.dw = dst_w;
+    const hipError_t err = launch_tiled(OP_RESIZE, 3, dst_t, j, make_gray_epilogue(border, border_value, norm),
+                                        (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "resize launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
+kr_status kr_warp_affine_gray(const void *src, int src_h, int src_w, size_t src_pitch, void *dst, int dst_h,
+                              int dst_w, kr_dtype dst_t, const double m[6], int flags, kr_border border,
+                              float border_value, const kr_normalize *norm, void *stream)
+{
+    clear_error();
+    kr_status s = check_gray(src, src_h, src_w, src_pitch, dst, dst_h, dst_w, dst_t, border, border_value, norm);
+    if (s != KR_OK)
+        return s;
+    if (flags & ~KR_WARP_INVERSE_MAP)
+        return fail(KR_ERR_INVALID_ARGUMENT, "unknown warp flags 0x%x", flags);
+    ImageJob j;
+    std::memset(&j, 0, sizeof j);
+    s = check_matrix(m, flags, j.inv);
+    if (s != KR_OK)
+        return s;
+    set_source(j, src, src_h, src_w, 3, KR_U8, src_pitch);
+    j.dst = dst; j.dh = dst_h; j.dw = dst_w;
+    const hipError_t err = launch_tiled(OP_WARP, 3, dst_t, j, make_gray_epilogue(border, border_value, norm),
+                                        (hipStream_t)stream);
+    if (err != hipSuccess)
+        return fail(KR_ERR_HIP, "warp launch failed: %s", hipGetErrorString(err));
+    return KR_OK;
+}
+
 kr_status kr_resize_nearest_view(const void *src, int src_h, int src_w, size_t src_pitch, int c, kr_dtype src_t,
                                  void *dst, int dst_h, int dst_w, kr_dtype dst_t, const kr_normalize *norm,
                                  void *stream)
@@ -325,8 +420,10 @@ kr_status kr_rgb_to_gray_view(const void *src, int h, int w, size_t src_pitch, k
             return fail(KR_ERR_INVALID_ARGUMENT, "normalisation has a bad mean/std");
     }
     const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
-    const uintptr_t s1 = s0 + source_span(h, w, 3, src_t, src_pitch);
-    const uintptr_t d1 = d0 + (uintptr_t)h * (uintptr_t)w * elem_size(dst_t);
+    const uintptr_t s1 = range_end(src, source_span(h, w, 3, src_t, src_pitch));
+    const uintptr_t d1 = range_end(dst, (size_t)h * (size_t)w * elem_size(dst_t));
+    if (!s1 || !d1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "src or dst range wraps past the end of the address space");
     if (s0 < d1 && d0 < s1)
         return fail(KR_ERR_INVALID_ARGUMENT, "src and dst overlap");
     ImageJob j;
@@ -467,7 +564,10 @@ kr_status kr_hbm_copy(void *dst, const void *src, size_t bytes, void *stream)
     if (reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
         return fail(KR_ERR_INVALID_ARGUMENT, "copy pointers must be 16-byte aligned");
     const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
-    if (s0 < d0 + bytes && d0 < s0 + bytes)
+    const uintptr_t s1 = range_end(src, bytes), d1 = range_end(dst, bytes);
+    if (!s1 || !d1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "copy range wraps past the end of the address space");
+    if (s0 < d1 && d0 < s1)
         return fail(KR_ERR_INVALID_ARGUMENT, "copy ranges overlap");
     if (bytes == 0)
         return KR_OK;
@@ -499,7 +599,10 @@ kr_status kr_hbm_stream(void *dst, size_t dst_bytes, const void *src, size_t src
     if (src_bytes > dst_bytes && lg > 8)
         return fail(KR_ERR_INVALID_ARGUMENT, "at most 256 input chunks per output chunk");
     const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
-    if (s0 < d0 + dst_bytes && d0 < s0 + src_bytes)
+    const uintptr_t s1 = range_end(src, src_bytes), d1 = range_end(dst, dst_bytes);
+    if (!s1 || !d1)
+        return fail(KR_ERR_INVALID_ARGUMENT, "stream range wraps past the end of the address space");
+    if (s0 < d1 && d0 < s1)
         return fail(KR_ERR_INVALID_ARGUMENT, "stream ranges overlap");
     const hipError_t err = launch_stream(dst, dst_bytes / 16, src, src_bytes > dst_bytes ? lg : 0,
                                          dst_bytes > src_bytes ? lg : 0, (hipStream_t)stream);

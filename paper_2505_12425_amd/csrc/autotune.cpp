@@ -98,10 +98,16 @@ kr_status kr_autotune_load(const char *text)
     clear_error();
     if (!text)
         return fail(KR_ERR_INVALID_ARGUMENT, "text is NULL");
-    if (!tune_load_text(text))
+    const int r = tune_load_text(text);
+    if (r == 1)
         return fail(KR_ERR_INVALID_ARGUMENT, "malformed tuning table line");
+    if (r == 2)
+        return fail(KR_ERR_UNSUPPORTED, "tuning table made for another build (this library: %s); ignored",
+                    tune_build_key());
     return KR_OK;
 }
+
+const char *kr_build_key(void) { return tune_build_key(); }
 
 void kr_autotune_clear(void) { tune_clear(); }
 

@@ -10,6 +10,7 @@
 // kr_resize_batch / kr_batch_plan_* (plans capture their launches in a HIP
 // graph; they record no memset nodes).
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -23,17 +24,17 @@
 
 namespace kr {
 
-template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT>
-__global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict__ jobs, int njobs, int ntiles,
+// PIPE: persistent grid (each workgroup walks its XCD's tile range,
+// prefetching the next tile); else at most one tile per workgroup.
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT, bool PIPE>
+__global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict__ jobs, int njobs, TileBins bins,
                                                       Epilogue e, TileGeom G)
 {
     extern __shared__ uint32_t lds[];
-    TileSeq seq(blockIdx.x, gridDim.x, ntiles);
-    // f32 outputs leave through non-temporal stores: faster here, where each
-    // tile writes rows of a small image; the single-image kernels keep plain
-    // stores, under which a reused output buffer stays partly in the
-    // last-level cache
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, false>(G, e, lds, [&](TiledJob &t, int &tile) {
+    TileSeq seq(blockIdx.x, gridDim.x, bins.start);
+    // f32 outputs leave through non-temporal stores (no kernel of the launch
+    // reads them back)
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, PIPE>(G, e, lds, [&](TiledJob &t, int &tile) {
         int g;
         if (!seq.take(g))
             return false;
@@ -54,9 +55,19 @@ __global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict
 template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
 static hipError_t launch_group_cfg(const BatchGroup &g, const Epilogue &e, hipStream_t s)
 {
-    // one workgroup per tile (batch configurations have no persistent mode)
-    auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 3>;
-    hipLaunchKernelGGL(kern, dim3(g.ntiles), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.ntiles, e, g.G);
+    int widest = 0;  // largest per-XCD tile range
+    for (int k = 0; k < 8; k++)
+        widest = std::max(widest, g.bins.start[k + 1] - g.bins.start[k]);
+    if (g.cfg.grid == GRID_PERSISTENT) {
+        auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 1, true>;
+        const long resident = (long)blocks_per_cu(reinterpret_cast<const void *>(kern), g.lds) * device_cus();
+        const int grid = (int)std::max(8L, std::min(8L * widest, resident & ~7L));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.bins, e, g.G);
+    } else {
+        auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 3, false>;
+        hipLaunchKernelGGL(kern, dim3(8 * std::max(widest, 1)), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs,
+                           g.bins, e, g.G);
+    }
     return hipGetLastError();
 }
 
@@ -92,44 +103,91 @@ hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue 
 
 constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's widest box
 
-// Primary tile shape of a batch group when the batch class is not tuned:
-// small tiles, so that batches of small outputs still produce many tiles.
+// Tile shape of a batch group when the batch class is not tuned: small
+// tiles, so that batches of small outputs still produce many tiles.
 static TileCfg default_batch_cfg(int op, bool f32)
 {
     (void)op;
-    return f32 ? TileCfg{1, 64, 1, 4, false} : TileCfg{4, 16, 1, 1, false};
+    return f32 ? TileCfg{1, 64, 1, 4, GRID_FULL} : TileCfg{4, 16, 1, 1, GRID_FULL};
 }
-
-// Secondary tile shape of warps whose boxes do not fit the primary one.
-static const TileCfg KB_SMALL_TILES{4, 8, 1, 1, false};
 
 static int cfg_tw(const TileCfg &c) { return c.txt * c.px * c.cpt; }
 static int cfg_th(const TileCfg &c) { return (KT_THREADS / c.txt) * c.rpt; }
 
-// One group: job table (tile prefix sums) and launch-wide LDS geometry, the
-// largest box among the items that are staged (stage[i]); the others, and
-// every item when gather is set, read their taps from global memory.
-static void build_group(int op, const TileCfg &cfg, bool gather, const std::vector<ImageJob> &imgs,
+// Estimated bytes an item moves: output bytes plus the source bytes its taps
+// touch (about the output's pixels times the source area per output pixel,
+// at most 4: beyond that the taps skip rows and columns); tiles that read
+// their taps from global memory count half again.
+static double item_cost(const ImageJob &j, int op, bool f32, int c, bool staged)
+{
+    const double px = (double)j.dh * (double)j.dw;
+    const double ratio = op == OP_RESIZE ? (double)j.sh * (double)j.sw / px
+                                         : std::fabs(j.inv[0] * j.inv[4] - j.inv[1] * j.inv[3]);
+    const double bytes = px * c * ((f32 ? 4.0 : 1.0) + std::min(ratio, 4.0));
+    return staged ? bytes : 1.5 * bytes;
+}
+
+// One group: job table (tile prefix sums, items ordered bin by bin), per-XCD
+// bins and the launch-wide LDS geometry, the largest box among the items
+// that are staged (stage[i]); the others read their taps from global memory.
+static void build_group(int op, const TileCfg &cfg, bool f32, int c, const std::vector<ImageJob> &imgs,
                         const std::vector<bool> &stage, BatchGroup &g, std::vector<TiledJob> &table)
 {
     g.op = op;
     g.cfg = cfg;
     const int tw = cfg_tw(cfg), th = cfg_th(cfg);
+    const int n = (int)imgs.size();
+    // longest processing time first: items by cost, largest first, each into
+    // the least loaded of the 8 bins
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; i++) {
+        order[i] = i;
+        cost[i] = item_cost(imgs[i], op, f32, c, stage[i]);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<int> bin_of(n);
+    for (int i : order) {
+        int k = 0;
+        for (int q = 1; q < 8; q++)
+            k = load[q] < load[k] ? q : k;
+        bin_of[i] = k;
+        load[k] += cost[i];
+    }
+    double total = 0, top = 0;
+    for (double l : load) {
+        total += l;
+        top = std::max(top, l);
+    }
+    // too few items to balance whole images (one large item, say): equal
+    // tile counts per XCD over the list in submission order instead
+    const bool by_item = n >= 8 && top <= 1.1 * total / 8.0;
     table.clear();
     g.G = TileGeom{0, 0};
     int first = 0;
-    for (size_t i = 0; i < imgs.size(); i++) {
-        const ImageJob &j = imgs[i];
-        TiledJob t = make_tiled_job(j, op, tw, th);
-        t.first_tile = first;
-        first += t.ntiles;
-        table.push_back(t);
-        if (gather || !stage[i])
-            continue;
-        const TileGeom Gi = tile_geom(j, op, tw, th);
-        g.G.pitch = std::max(g.G.pitch, Gi.pitch);
-        g.G.rows = std::max(g.G.rows, Gi.rows);
+    for (int k = 0; k < 8; k++) {
+        g.bins.start[k] = first;
+        for (int q = 0; q < n; q++) {
+            const int i = by_item ? order[q] : q;
+            if (by_item ? bin_of[i] != k : k != 0)
+                continue;
+            const ImageJob &j = imgs[i];
+            TiledJob t = make_tiled_job(j, op, tw, th);
+            t.first_tile = first;
+            first += t.ntiles;
+            table.push_back(t);
+            if (!stage[i])
+                continue;
+            const TileGeom Gi = tile_geom(j, op, tw, th);
+            g.G.pitch = std::max(g.G.pitch, Gi.pitch);
+            g.G.rows = std::max(g.G.rows, Gi.rows);
+        }
     }
+    g.bins.start[8] = first;
+    if (!by_item)
+        for (int k = 0; k <= 8; k++)
+            g.bins.start[k] = (int)((long)first * k / 8);
     g.njobs = (int)table.size();
     g.ntiles = first;
     g.lds = tile_lds_bytes(g.G, tw, th);
@@ -140,11 +198,12 @@ static bool fits(const ImageJob &j, int op, const TileCfg &c, size_t budget)
     return tile_lds_bytes(tile_geom(j, op, cfg_tw(c), cfg_th(c)), cfg_tw(c), cfg_th(c)) <= budget;
 }
 
-// Resizes form one group: their boxes are predictable, and tiles whose box
-// does not fit (large ratios) take the gather path inside the same launch.
-// Warps are split three ways (primary / 32x32 tiles / gather), so that a few
-// strongly shrinking items neither force the gather path on all of their
-// tiles nor raise every workgroup's LDS footprint.
+// One group per operation.  Resizes that shrink x by 2 or more share no taps
+// between neighbouring outputs, while their boxes (over twice the tile width)
+// would set the LDS size of every workgroup of the launch: such items read
+// their taps directly, which keeps the group's LDS and so its occupancy at the
+// size the milder items need.  Warps whose boxes exceed the batch LDS budget
+// (strong shrinks) likewise take the global-gather path for their tiles.
 void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const TileCfg *const force[2], BatchBuild &b)
 {
     b.groups.clear();
@@ -160,38 +219,14 @@ void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const Til
             P = tuned;
         else
             P = default_batch_cfg(op, f32);
-        if (op == OP_RESIZE) {
-            // An item that shrinks x by 2 or more shares no taps between
-            // neighbouring outputs, while its box (over twice the tile width)
-            // would set the LDS size of every workgroup of the launch: such
-            // items read their taps directly, which keeps the group's LDS and
-            // so its occupancy at the size the milder items need.
-            std::vector<bool> stage;
-            for (const ImageJob &j : imgs[k])
-                stage.push_back(!wants_gather(j, op) && (double)j.sw < 2.0 * (double)j.dw &&
-                                fits(j, op, P, KB_LDS_BUDGET));
-            b.groups.emplace_back();
-            b.tables.emplace_back();
-            build_group(op, P, false, imgs[k], stage, b.groups.back(), b.tables.back());
-            continue;
-        }
-        std::vector<ImageJob> cls[3];  // primary, small tiles, gather
-        for (const ImageJob &j : imgs[k]) {
-            if (fits(j, op, P, KB_LDS_BUDGET))
-                cls[0].push_back(j);
-            else if (fits(j, op, KB_SMALL_TILES, KT_LDS_CAP))
-                cls[1].push_back(j);
-            else
-                cls[2].push_back(j);
-        }
-        for (int q = 0; q < 3; q++) {
-            if (cls[q].empty())
-                continue;
-            b.groups.emplace_back();
-            b.tables.emplace_back();
-            build_group(op, q == 1 ? KB_SMALL_TILES : P, q == 2, cls[q], std::vector<bool>(cls[q].size(), true),
-                        b.groups.back(), b.tables.back());
-        }
+        std::vector<bool> stage;
+        for (const ImageJob &j : imgs[k])
+            stage.push_back(op == OP_RESIZE ? !wants_gather(j, op) && (double)j.sw < 2.0 * (double)j.dw &&
+                                                  fits(j, op, P, KB_LDS_BUDGET)
+                                            : fits(j, op, P, KB_LDS_BUDGET));
+        b.groups.emplace_back();
+        b.tables.emplace_back();
+        build_group(op, P, f32, c, imgs[k], stage, b.groups.back(), b.tables.back());
     }
 }
 
@@ -425,7 +460,8 @@ extern "C" kr_status kr_resize_batch_noalloc(const kr_batch_item *items, int n, 
 struct kr_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void *table = nullptr;  // device job tables
+    void *table = nullptr;      // device job tables
+    hipEvent_t last = nullptr;  // recorded after each replay
     int ntiles = 0;
 };
 
@@ -439,6 +475,8 @@ static void plan_free(kr_batch_plan *p)
         (void)hipGraphDestroy(p->graph);
     if (p->table)
         (void)hipFree(p->table);
+    if (p->last)
+        (void)hipEventDestroy(p->last);
     delete p;
 }
 
@@ -480,7 +518,9 @@ kr_status kr_batch_plan_create_ex(const kr_batch_item *items, int n, int c, kr_d
     build_batch(imgs, f32, c, none, bb);
     std::vector<uint8_t> host(bb.bytes());
     bb.pack(host.data());
-    hipError_t err = hipMalloc(&p->table, host.size());
+    hipError_t err = hipEventCreateWithFlags(&p->last, hipEventDisableTiming);
+    if (err == hipSuccess)
+        err = hipMalloc(&p->table, host.size());
     if (err != hipSuccess) {
         plan_free(p);
         return fail(KR_ERR_HIP, "plan allocation failed: %s", hipGetErrorString(err));
@@ -522,7 +562,14 @@ kr_status kr_batch_plan_launch(kr_batch_plan *plan, void *stream)
     clear_error();
     if (!plan || !plan->exec)
         return fail(KR_ERR_INVALID_ARGUMENT, "plan is NULL");
-    const hipError_t err = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    // replays of one plan write the same outputs: each is ordered after the
+    // previous one (on whichever stream that ran), so the event recorded
+    // after the latest replay completes only after all of them
+    hipError_t err = hipStreamWaitEvent((hipStream_t)stream, plan->last, 0);
+    if (err == hipSuccess)
+        err = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (err == hipSuccess)
+        err = hipEventRecord(plan->last, (hipStream_t)stream);
     if (err != hipSuccess)
         return fail(KR_ERR_HIP, "plan launch failed: %s", hipGetErrorString(err));
     return KR_OK;
@@ -532,7 +579,9 @@ void kr_batch_plan_destroy(kr_batch_plan *plan)
 {
     if (!plan)
         return;
-    (void)hipDeviceSynchronize();
+    // waits for this plan's own replays only (not the whole device)
+    if (plan->last)
+        (void)hipEventSynchronize(plan->last);
     plan_free(plan);
 }
 

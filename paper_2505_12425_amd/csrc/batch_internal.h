@@ -9,21 +9,26 @@
 
 namespace kr {
 
-// One operation group of a batch, ready to launch.
+// One operation group of a batch, ready to launch.  Its job table lists the
+// items bin by bin: bins[k] is the tile range of XCD k, filled by longest
+// processing time first (items by estimated bytes, largest first, each into
+// the least loaded bin), so that the eight XCDs get equal shares of the work
+// while each image's tiles stay on one XCD's L2.
 struct BatchGroup {
     int op = OP_RESIZE;
-    TileCfg cfg{4, 16, 1, 1, false};
+    TileCfg cfg{4, 16, 1, 1, GRID_FULL};
     TileGeom G{0, 0};
     int njobs = 0;
     int ntiles = 0;
+    TileBins bins{};
     size_t lds = 0;
     const TiledJob *jobs_dev = nullptr;  // device copy of the job table
 };
 
-// Every launch of a batch: one group for the resizes; for the warps up to
-// three, by LDS class: boxes that fit the primary tile shape (tuned or
-// default) within the batch LDS budget, boxes that fit 32x32 tiles within the
-// LDS cap, and the rest (global-gather path, no LDS).
+// Every launch of a batch: one group (one launch) per operation.  Items whose
+// source boxes fit the group's tile shape within the batch LDS budget are
+// staged through LDS; the tiles of the others read their taps from global
+// memory in the same launch.
 struct BatchBuild {
     std::vector<BatchGroup> groups;
     std::vector<std::vector<TiledJob>> tables;

@@ -19,6 +19,11 @@ hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, con
 
 hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
+    // pixel permutations (flips, quarter turns, transposes with whole offsets)
+    // of u8 sources: the same bits without interpolation
+    int m[6];
+    if (st == KR_U8 && !e.planar && !e.gray && permutation_map(j, m))
+        return launch_permute(c, dt, j, m, e, s);
     if (tiled_supported(c, st))
         return launch_tiled(OP_WARP, c, dt, j, e, s);
     return launch_generic(OP_WARP, c, st, dt, j, e, s);

@@ -24,6 +24,13 @@ kr_status check_source(const void *src, int h, int w, int c, kr_dtype st, size_t
 void set_source(ImageJob &j, const void *src, int h, int w, int c, kr_dtype st, size_t pitch);
 // Bytes from a source's first byte to its last one, plus one.
 size_t source_span(int h, int w, int c, kr_dtype st, size_t pitch);
+// One past the last byte of [p, p + n), or 0 if the range wraps past the top
+// of the address space (no such buffer exists: the caller rejects it).
+inline uintptr_t range_end(const void *p, size_t n)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p), e = a + n;
+    return e < a ? 0 : e;
+}
 Epilogue make_epilogue(int c, kr_border border, float bval, const kr_normalize *norm);
 kr_status check_matrix(const double m[6], int flags, double inv[6]);
 kr_status invert_affine_impl(const double m[6], double inv[6]);

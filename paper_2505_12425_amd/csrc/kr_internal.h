@@ -20,6 +20,9 @@ struct Epilogue {
     int bval_i;      // CONSTANT border value as an integer sample (u8 path)
     int border;      // KR_BORDER_CONSTANT or KR_BORDER_REPLICATE
     int planar;      // output layout: 0 = interleaved (HWC), 1 = planar (CHW, plane c at c * dh * dw)
+    int gray;        // RGB source, one BT.601 gray channel out (the channel values are
+                     // then unnormalised: alpha 1, beta 0; galpha, gbeta normalise the gray)
+    float galpha, gbeta;
 };
 
 // One image as the kernels see it.  For warps, inv is the inverse map with
@@ -54,6 +57,13 @@ hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const
                        hipStream_t s);
 hipError_t launch_persp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e,
                         hipStream_t s);
+// Affine warps whose inverse map permutes pixels (permute.hip): the map's
+// whole-number coefficients, when A, B, D, E are -1, 0 or 1 with one non-zero
+// per row and column and C, F are whole numbers.
+bool permutation_map(const ImageJob &j, int (&m)[6]);
+hipError_t launch_permute(int c, kr_dtype dt, const ImageJob &j, const int (&m)[6], const Epilogue &e, hipStream_t s);
+// The LDS-tiled kernels (u8 sources with 3 or 4 channels) directly.
+hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Traffic-mix probe: shrink > 0 reads 2^shrink input chunks per output chunk,
 // grow > 0 reads one input chunk for 2^grow output chunks (at most one of them

@@ -59,13 +59,18 @@ struct HipExec {
         if (bytes > table_cap)
             return false;
         bb.pack(static_cast<uint8_t *>(sl.staging));
-        if (hipMemcpyAsync(sl.table, sl.staging, bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
-            return false;
+        // On a failure after something was enqueued, the scheduler releases
+        // the batch's output blocks and requeues its requests, and the slot's
+        // staging buffer may be repacked at once: wait for what this slot
+        // already has in flight before reporting it.
+        bool ok = hipMemcpyAsync(sl.table, sl.staging, bytes, hipMemcpyHostToDevice, sl.stream) == hipSuccess;
         bb.bind(sl.table);
-        for (const BatchGroup &g : bb.groups)
-            if (launch_group(g, c, dt, e, sl.stream) != hipSuccess)
-                return false;
-        return hipEventRecord(sl.done, sl.stream) == hipSuccess;
+        for (size_t g = 0; ok && g < bb.groups.size(); g++)
+            ok = launch_group(bb.groups[g], c, dt, e, sl.stream) == hipSuccess;
+        ok = ok && hipEventRecord(sl.done, sl.stream) == hipSuccess;
+        if (!ok)
+            (void)hipStreamSynchronize(sl.stream);
+        return ok;
     }
 
     bool done(int s) { return hipEventQuery(slots[s].done) == hipSuccess; }

@@ -431,14 +431,80 @@ __device__ __forceinline__ void store_run_f32(float *row, int x, int x_end, bool
     }
 }
 
+// BT.601 luma of an RGB pixel (byte c = channel c): u8 with 14-bit weights
+// (summing to 2^14, so grey stays grey), rounded half up; f32 in binary32
+// with the fma chain of the standalone RGB -> gray kernel, so that a fused
+// gray equals resampling followed by that kernel, bit for bit.
+__device__ __forceinline__ uint32_t luma_u8(uint32_t p)
+{
+    const uint32_t acc = 4899u * (p & 0xFFu) + 9617u * ((p >> 8) & 0xFFu) + 1868u * ((p >> 16) & 0xFFu);
+    return (acc + 8192u) >> 14;
+}
+
+__device__ __forceinline__ float luma_f32(float r, float g, float b)
+{
+    return __builtin_fmaf(0.114f, b, __builtin_fmaf(0.587f, g, 0.299f * r));
+}
+
+// Gray output (one channel, row y of dw pixels): the lane's PX pixels from
+// their RGB results.  4-pixel runs are one dword (u8) or one 16-byte vector
+// (f32) when the row width is a multiple of 4.
+template <int PX>
+__device__ __forceinline__ void store_gray_u8(const ImageJob &j, int y, int x, int x_end, const uint32_t (&P)[PX])
+{
+    uint8_t *row = static_cast<uint8_t *>(j.dst) + (size_t)y * (size_t)j.dw;
+    const int n = min(PX, x_end - x);
+    if (n <= 0)
+        return;
+    if constexpr (PX == 4) {
+        if (n == 4 && (j.dw & 3) == 0) {
+            *reinterpret_cast<uint32_t *>(row + x) =
+                luma_u8(P[0]) | (luma_u8(P[1]) << 8) | (luma_u8(P[2]) << 16) | (luma_u8(P[3]) << 24);
+            return;
+        }
+    }
+    for (int k = 0; k < n; k++)
+        row[x + k] = (uint8_t)luma_u8(P[k]);
+}
+
+template <int C, int PX, bool NT>
+__device__ __forceinline__ void store_gray_f32(const ImageJob &j, const Epilogue &e, int y, int x, int x_end,
+                                               const float (&o)[PX][C])
+{
+    float *row = static_cast<float *>(j.dst) + (size_t)y * (size_t)j.dw;
+    const int n = min(PX, x_end - x);
+    if (n <= 0)
+        return;
+    float g[PX];
+#pragma unroll
+    for (int k = 0; k < PX; k++)
+        g[k] = __builtin_fmaf(luma_f32(o[k][0], o[k][1], o[k][2]), e.galpha, e.gbeta);
+    if constexpr (PX == 4) {
+        if (n == 4 && (j.dw & 3) == 0) {
+            put<NT>(reinterpret_cast<f32x4 *>(row + x), f32x4{g[0], g[1], g[2], g[3]});
+            return;
+        }
+    }
+    for (int k = 0; k < n; k++)
+        put<NT>(row + x + k, g[k]);
+}
+
 // Store one lane run of output row y, interleaved (HWC, through the runs
 // above) or planar (CHW: channel c of pixel (x, y) at c * dh * dw + y * dw +
 // x; a 4-pixel run is one dword (u8) or one 16-byte vector (f32) per plane
-// when the row width is a multiple of 4).  The branch is uniform per launch.
+// when the row width is a multiple of 4), or as one gray channel.  The
+// branches are uniform per launch.
 template <int C, int PX>
-__device__ __forceinline__ void store_row_u8(const ImageJob &j, bool planar, int y, int x, int x_end, bool aligned,
-                                             const uint32_t (&P)[PX], uint32_t sel)
+__device__ __forceinline__ void store_row_u8(const ImageJob &j, const Epilogue &e, int y, int x, int x_end,
+                                             bool aligned, const uint32_t (&P)[PX], uint32_t sel)
 {
+    const bool planar = e.planar;
+    if constexpr (C == 3) {
+        if (e.gray) {
+            store_gray_u8<PX>(j, y, x, x_end, P);
+            return;
+        }
+    }
     if (!planar) {
         store_run_u8<C, PX>(static_cast<uint8_t *>(j.dst) + (size_t)y * (size_t)j.dw * C, x, x_end, aligned, P, sel);
         return;
@@ -464,9 +530,16 @@ __device__ __forceinline__ void store_row_u8(const ImageJob &j, bool planar, int
 }
 
 template <int C, int PX, bool NT = false>
-__device__ __forceinline__ void store_row_f32(const ImageJob &j, bool planar, int y, int x, int x_end, bool aligned,
-                                              const float (&o)[PX][C])
+__device__ __forceinline__ void store_row_f32(const ImageJob &j, const Epilogue &e, int y, int x, int x_end,
+                                              bool aligned, const float (&o)[PX][C])
 {
+    const bool planar = e.planar;
+    if constexpr (C == 3) {
+        if (e.gray) {
+            store_gray_f32<C, PX, NT>(j, e, y, x, x_end, o);
+            return;
+        }
+    }
     if (!planar) {
         size_t off = (size_t)y * (size_t)j.dw * C;
         if constexpr (PX == 1)
@@ -742,16 +815,19 @@ __device__ __noinline__ void write_tail_group(uint32_t *d, const uint8_t *src, i
         d[i] = load_px_bytes<C>(src, (size_t)(p0 + i));
 }
 
-// Issue the loads of this thread's first MAXIT work items of a tile.
-template <int OP, int C, int MAXIT>
-__device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const TileGeom &G, Prefetch<C, MAXIT> &pf)
+// Issue the loads of this thread's first MAXIT work items of a tile.  The
+// staging threads are numbered lt = 0 .. NLT - 1: the whole workgroup, or
+// the loader wave of a wave-specialised workgroup.
+template <int OP, int C, int MAXIT, int NLT = KT_THREADS>
+__device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const TileGeom &G, Prefetch<C, MAXIT> &pf,
+                                         int lt)
 {
     const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
     const int lo = t.j.sk, hi = src_end(t.j);
     const int total = p.nslots * p.ng;
 #pragma unroll
     for (int it = 0; it < MAXIT; it++) {
-        const int k = threadIdx.x + it * KT_THREADS;
+        const int k = lt + it * NLT;
         pf.dst[it] = -1;
         int dst, p0;
         if (k < total && group_of<OP>(t, p, G, k, dst, p0)) {
@@ -764,10 +840,10 @@ __device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const
 }
 
 // Write the prefetched groups to LDS, then stage any remaining work items
-// directly (boxes larger than MAXIT groups per thread).
-template <int OP, int C, int MAXIT>
+// directly (boxes larger than MAXIT groups per thread), MAXIT at a time.
+template <int OP, int C, int MAXIT, int NLT = KT_THREADS>
 __device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const TileGeom &G,
-                                       const Prefetch<C, MAXIT> &pf, uint32_t *lds)
+                                       Prefetch<C, MAXIT> &pf, uint32_t *lds, int lt)
 {
     const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
     const int lo = t.j.sk, hi = src_end(t.j);
@@ -781,16 +857,27 @@ __device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const T
         }
     }
     const int total = p.nslots * p.ng;
-    for (int k = threadIdx.x + MAXIT * KT_THREADS; k < total; k += KT_THREADS) {
-        int dst, p0;
-        if (!group_of<OP>(t, p, G, k, dst, p0))
-            continue;
-        if (p0 >= lo && p0 + 16 <= hi) {
-            GroupRegs<C> r;
-            load_group<C>(src, p0, r);
-            write_group<C>(lds + dst, r);
-        } else {
-            write_tail_group<C>(lds + dst, src, p0, lo, hi);
+    for (int k0 = lt + MAXIT * NLT; k0 < total; k0 += MAXIT * NLT) {
+#pragma unroll
+        for (int it = 0; it < MAXIT; it++) {
+            const int k = k0 + it * NLT;
+            pf.dst[it] = -1;
+            int dst, p0;
+            if (k < total && group_of<OP>(t, p, G, k, dst, p0)) {
+                pf.dst[it] = dst;
+                pf.p0[it] = p0;
+                if (p0 >= lo && p0 + 16 <= hi)
+                    load_group<C>(src, p0, pf.g[it]);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < MAXIT; it++) {
+            if (pf.dst[it] >= 0) {
+                if (pf.p0[it] >= lo && pf.p0[it] + 16 <= hi)
+                    write_group<C>(lds + pf.dst[it], pf.g[it]);
+                else
+                    write_tail_group<C>(lds + pf.dst[it], src, pf.p0[it], lo, hi);
+            }
         }
     }
 }
@@ -803,8 +890,9 @@ __device__ __forceinline__ bool needs_edge_fill(const TiledJob &t, const Plan &p
            (p.bx0 < 0 || p.bx0 + p.bw - 1 > t.j.sw - 1);
 }
 
-template <int OP, int C>
-__device__ __forceinline__ void fill_edge_columns(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds)
+template <int OP, int C, int NLT = KT_THREADS>
+__device__ __forceinline__ void fill_edge_columns(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds,
+                                                  int lt)
 {
     const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
     const int W = t.j.sw;
@@ -812,7 +900,7 @@ __device__ __forceinline__ void fill_edge_columns(const TiledJob &t, const Plan 
     const int last = p.bx0 + p.bw - 1;
     const int nr = last > W - 1 ? last - (W - 1) : 0;
     const int per = nl + nr;
-    for (int k = threadIdx.x; k < p.nslots * per; k += KT_THREADS) {
+    for (int k = lt; k < p.nslots * per; k += NLT) {
         const int s = udiv_small(k, per);
         const int jj = k - s * per;
         const int col = jj < nl ? jj : p.bw - nr + (jj - nl);
@@ -824,12 +912,13 @@ __device__ __forceinline__ void fill_edge_columns(const TiledJob &t, const Plan 
 
 // Resize tables after the box: per column (x0 - bx0 + margin, weights) and per
 // output row (y0, weight).  F32: weights are the fraction's bit pattern.
-template <int TW, int TH, bool F32>
-__device__ __forceinline__ void resize_tables(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds)
+template <int TW, int TH, bool F32, int NLT = KT_THREADS>
+__device__ __forceinline__ void resize_tables(const TiledJob &t, const Plan &p, const TileGeom &G, uint32_t *lds,
+                                              int lt)
 {
     const ImageJob &j = t.j;
     uint32_t *tab = lds + G.rows * G.pitch + KT_MARGIN;
-    for (int i = threadIdx.x; i < TW + TH; i += KT_THREADS) {
+    for (int i = lt; i < TW + TH; i += NLT) {
         int i0, w1;
         float f;
         if (i < TW) {
@@ -955,7 +1044,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                     }
                     P[k] = pack_px<C>(v);
                 }
-                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e, y, xr, x_end, aligned, P, sel);
             } else {
                 float o[PX][C];
 #pragma unroll
@@ -1002,7 +1091,7 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                     interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
                                         extra, ev, o[k]);
                 }
-                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e, y, xr, x_end, aligned, o);
             }
         }
     }
@@ -1075,7 +1164,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                     }
                     P[k] = pack_px<C>(v);
                 }
-                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e, y, xr, x_end, aligned, P, sel);
             } else {
                 const float fy = __builtin_bit_cast(float, rw);
                 float o[PX][C];
@@ -1095,7 +1184,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                     interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
                                         extra, ev, o[k]);
                 }
-                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e, y, xr, x_end, aligned, o);
             }
         }
     }
@@ -1299,9 +1388,9 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
                     gather_px_f32<C>(j, e, x0, y0, fx, fy, o[k]);
             }
             if constexpr (!F32)
-                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e, y, xr, x_end, aligned, P, sel);
             else
-                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e, y, xr, x_end, aligned, o);
         }
     }
 }
@@ -1336,9 +1425,9 @@ __device__ __forceinline__ void fill_blank(const TiledJob &t, const Plan &p, con
         for (int c = 0; c < CPT; c++) {
             const int xr = p.ox0 + c * L::SEG + L::col0();
             if constexpr (!F32)
-                store_row_u8<C, PX>(j, e.planar, y, xr, x_end, aligned, P, sel);
+                store_row_u8<C, PX>(j, e, y, xr, x_end, aligned, P, sel);
             else
-                store_row_f32<C, PX, L::NT>(j, e.planar, y, xr, x_end, aligned, o);
+                store_row_f32<C, PX, L::NT>(j, e, y, xr, x_end, aligned, o);
         }
     }
 }
@@ -1362,14 +1451,14 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
     if constexpr (!PIPE) {
         if (!p.direct) {
             Prefetch<C, MAXIT> pf;
-            prefetch<OP, C, MAXIT>(t, p, G, pf);
-            commit<OP, C, MAXIT>(t, p, G, pf, lds);
+            prefetch<OP, C, MAXIT>(t, p, G, pf, threadIdx.x);
+            commit<OP, C, MAXIT>(t, p, G, pf, lds, threadIdx.x);
         }
         if constexpr (OP == OP_RESIZE)
-            resize_tables<TW, TH, F32>(t, p, G, lds);
+            resize_tables<TW, TH, F32>(t, p, G, lds, threadIdx.x);
         __syncthreads();
         if (needs_edge_fill(t, p, e)) {
-            fill_edge_columns<OP, C>(t, p, G, lds);
+            fill_edge_columns<OP, C>(t, p, G, lds, threadIdx.x);
             __syncthreads();
         }
         if (p.blank)
@@ -1383,15 +1472,15 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         return;
     }
     Prefetch<C, MAXIT> pf;
-    prefetch<OP, C, MAXIT>(t, p, G, pf);
+    prefetch<OP, C, MAXIT>(t, p, G, pf, threadIdx.x);
     while (true) {
         if (!p.direct)
-            commit<OP, C, MAXIT>(t, p, G, pf, lds);
+            commit<OP, C, MAXIT>(t, p, G, pf, lds, threadIdx.x);
         if constexpr (OP == OP_RESIZE)
-            resize_tables<TW, TH, F32>(t, p, G, lds);
+            resize_tables<TW, TH, F32>(t, p, G, lds, threadIdx.x);
         __syncthreads();
         if (needs_edge_fill(t, p, e)) {
-            fill_edge_columns<OP, C>(t, p, G, lds);
+            fill_edge_columns<OP, C>(t, p, G, lds, threadIdx.x);
             __syncthreads();
         }
         TiledJob nt;
@@ -1400,7 +1489,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         Plan np;
         if (more) {
             np = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
-            prefetch<OP, C, MAXIT>(nt, np, G, pf);
+            prefetch<OP, C, MAXIT>(nt, np, G, pf, threadIdx.x);
         }
         if (p.blank)
             fill_blank<C, F32, L>(t, p, e);
@@ -1415,6 +1504,84 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         __syncthreads();
         t = nt;
         p = np;
+    }
+}
+
+// Wave-specialised tile pipeline: the workgroup has KT_THREADS compute
+// threads (the lane layout L) plus one loader wave (threads KT_THREADS ..
+// KT_THREADS + 63), and two LDS buffers of buf_dwords each.  The loader wave
+// stages tile i into buffer i & 1 (loads, LDS writes, edge columns, resize
+// tables) and issues the first loads of tile i + 1; the compute waves
+// interpolate tile i and store it.  One barrier per tile: when both sides
+// reach barrier i, tile i is staged and tile i - 1 has been consumed, so the
+// loader may overwrite the buffer tile i - 1 used.
+//
+// Why: on this architecture one counter tracks a wave's outstanding loads and
+// stores together, so a wave that waits for its staging loads also waits for
+// every store it issued before them.  Here the compute waves issue no loads
+// (gather tiles aside) and never wait on their stores; the loader wave issues
+// no stores.  Every wave of the workgroup takes the same tile sequence and
+// computes the same tile plans, so both sides execute the same number of
+// barriers.
+template <int OP, int C, bool F32, class L, int MAXIT, typename NextJob>
+__device__ __forceinline__ void run_tiles_ws(const TileGeom &G, const Epilogue &e, uint32_t *lds, int buf_dwords,
+                                             NextJob next_job)
+{
+    constexpr int TW = L::TW;
+    constexpr int TH = L::TH;
+    TiledJob t;
+    int tile;
+    if (!next_job(t, tile))
+        return;
+    const bool cb = e.border == KR_BORDER_CONSTANT;
+    Plan p = make_plan<OP, TW, TH, F32>(t, tile, G, cb);
+    if (__builtin_amdgcn_readfirstlane((int)threadIdx.x) >= KT_THREADS) {
+        const int lt = lane_id();
+        Prefetch<C, MAXIT> pf;
+        if (!p.direct)
+            prefetch<OP, C, MAXIT, 64>(t, p, G, pf, lt);
+        for (int i = 0;; i++) {
+            uint32_t *buf = lds + (i & 1) * buf_dwords;
+            if (!p.direct)
+                commit<OP, C, MAXIT, 64>(t, p, G, pf, buf, lt);
+            if constexpr (OP == OP_RESIZE)
+                resize_tables<TW, TH, F32, 64>(t, p, G, buf, lt);
+            // the edge columns overwrite what the group writes above spilled
+            // there; one wave's LDS writes complete in order
+            if (needs_edge_fill(t, p, e))
+                fill_edge_columns<OP, C, 64>(t, p, G, buf, lt);
+            TiledJob nt;
+            int ntile;
+            const bool more = next_job(nt, ntile);
+            if (more) {
+                p = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
+                if (!p.direct)
+                    prefetch<OP, C, MAXIT, 64>(nt, p, G, pf, lt);
+                t = nt;
+            }
+            __syncthreads();
+            if (!more)
+                break;
+        }
+    } else {
+        for (int i = 0;; i++) {
+            __syncthreads();
+            const uint32_t *buf = lds + (i & 1) * buf_dwords;
+            if (p.blank)
+                fill_blank<C, F32, L>(t, p, e);
+            else if (p.direct)
+                compute_gather<OP, C, F32, L>(t, p, G, e, buf);
+            else if constexpr (OP == OP_RESIZE)
+                compute_resize<C, F32, L>(t, p, G, e, buf);
+            else
+                compute_warp<C, F32, L, OP == OP_PERSP>(t, p, G, e, buf);
+            TiledJob nt;
+            int ntile;
+            if (!next_job(nt, ntile))
+                break;
+            t = nt;
+            p = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
+        }
     }
 }
 
@@ -1439,6 +1606,17 @@ struct TileSeq {
             end = start + q + (k < r ? 1 : 0);
         }
     }
+    // Tile ranges given per XCD: XCD k (blocks b = k mod 8) owns tiles
+    // [start[k], start[k + 1]) and its blocks interleave over them.  grid is
+    // a multiple of 8; with grid / 8 >= the largest range each block takes at
+    // most one tile.
+    __device__ __forceinline__ TileSeq(int b, int grid, const int (&start)[9])
+    {
+        const int k = b & 7;
+        next = start[k] + (b >> 3);
+        step = grid >> 3;
+        end = start[k + 1];
+    }
     __device__ __forceinline__ bool take(int &tile)
     {
         if (next >= end)
@@ -1447,6 +1625,11 @@ struct TileSeq {
         next += step;
         return true;
     }
+};
+
+// Per-XCD tile ranges of a batch launch (TileSeq above).
+struct TileBins {
+    int start[9];
 };
 
 }  // namespace kr

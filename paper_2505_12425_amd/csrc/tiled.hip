@@ -33,6 +33,22 @@ __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, 
     });
 }
 
+// Wave-specialised persistent grid: KT_THREADS compute threads plus one
+// loader wave; the dynamic LDS holds two buffers of buf_dwords each.
+template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT>
+__global__ __launch_bounds__(KT_THREADS + 64) void k_tiled_ws(TiledJob job, Epilogue e, TileGeom G, int buf_dwords)
+{
+    extern __shared__ uint32_t lds[];
+    TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
+    run_tiles_ws<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT>(G, e, lds, buf_dwords,
+                                                                     [&](TiledJob &t, int &tile) {
+        if (!seq.take(tile))
+            return false;
+        t = job;
+        return true;
+    });
+}
+
 int device_cus()
 {
     static std::atomic<int> cus[64];  // 0 = not queried yet (static storage starts zeroed)
@@ -51,7 +67,7 @@ int device_cus()
 // Resident workgroups per CU for a kernel at a dynamic LDS size, cached per
 // device, kernel and kilobyte of LDS (the kernels share one signature, so the
 // key holds the kernel's address).
-static int blocks_per_cu(const void *kernel, size_t lds)
+int blocks_per_cu(const void *kernel, size_t lds, int threads)
 {
     static std::mutex mu;
     static std::map<std::tuple<int, const void *, size_t>, int> cache;
@@ -69,7 +85,7 @@ static int blocks_per_cu(const void *kernel, size_t lds)
             return it->second;
     }
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, KT_THREADS, slot * 1024) != hipSuccess || n < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, slot * 1024) != hipSuccess || n < 1)
         n = 1;
     std::lock_guard<std::mutex> g(mu);
     cache[key] = n;
@@ -268,7 +284,7 @@ size_t tile_lds_bytes(const TileGeom &G, int tw, int th)
 }
 
 template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT>
-static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s, bool persistent, bool gather,
+static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s, int mode, bool gather,
                              bool &fits)
 {
     using L = Layout<PX, TXT, CPT, RPT>;
@@ -283,10 +299,24 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
         G.rows = 0;
     }
     const size_t lds = tile_lds_bytes(G, TW, TH);
+    if (mode == GRID_WS) {
+        // two buffers, each a whole number of 16-byte rows apart
+        const int buf_dwords = (int)((lds / 4 + 3) & ~(size_t)3);
+        fits = 8 * (size_t)buf_dwords <= KT_LDS_CAP;
+        if (!fits)
+            return hipSuccess;
+        constexpr int MAXIT_WS = 4;  // groups in flight per loader lane
+        auto kern = k_tiled_ws<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_WS>;
+        const size_t bytes = 8 * (size_t)buf_dwords;
+        const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), bytes,
+                                                                 KT_THREADS + 64));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS + 64), bytes, s, t, e, G, buf_dwords);
+        return hipGetLastError();
+    }
     fits = lds <= KT_LDS_CAP;
     if (!fits)
         return hipSuccess;
-    if (persistent) {
+    if (mode == GRID_PERSISTENT) {
         auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_PERS, true>;
         const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), lds));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
@@ -303,7 +333,7 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 {
 #define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
     if (cfg.px == PX && cfg.txt == TXT && cfg.cpt == CPT && cfg.rpt == RPT)                              \
-        return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.persistent, gather, fits);
+        return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.grid, gather, fits);
     if constexpr (OP != OP_RESIZE) {
         KR_WARP_CFGS(KR_TRY)
     } else {
@@ -315,20 +345,23 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 }
 
 // Tile shapes tried in order (the first whose LDS footprint fits is used).
-// KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent" override the
+// KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent"|"ws" override the
 // first choice.
 static int default_cfgs(int op, bool f32, TileCfg *out)
 {
     int n = 0;
     const char *tile = std::getenv("KR_TILE");
     const char *grid = std::getenv("KR_GRID");
-    const bool force_full = grid && std::strcmp(grid, "full") == 0;
-    const bool force_pers = grid && std::strcmp(grid, "persistent") == 0;
+    int force = -1;
+    if (grid)
+        force = std::strcmp(grid, "full") == 0 ? GRID_FULL
+                : std::strcmp(grid, "persistent") == 0 ? GRID_PERSISTENT
+                : std::strcmp(grid, "ws") == 0 ? GRID_WS : -1;
     int px = 0, txt = 0, cpt = 0, rpt = 0;
     if (tile && std::sscanf(tile, "%dx%dx%dx%d", &px, &txt, &cpt, &rpt) == 4)
-        out[n++] = TileCfg{px, txt, cpt, rpt, !force_full};
+        out[n++] = TileCfg{px, txt, cpt, rpt, force >= 0 ? force : GRID_PERSISTENT};
     auto add = [&](int a, int b, int c, int d, bool pers) {
-        out[n++] = TileCfg{a, b, c, d, force_pers ? true : (force_full ? false : pers)};
+        out[n++] = TileCfg{a, b, c, d, force >= 0 ? force : (pers ? GRID_PERSISTENT : GRID_FULL)};
     };
     // the autotuner's choices on MI355X for 4K sources (3840x2160x3 u8, every
     // source read from HBM): f32 warps run best on a persistent grid of 16-row

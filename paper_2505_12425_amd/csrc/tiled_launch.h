@@ -11,12 +11,18 @@ struct TileGeom;
 
 constexpr size_t KT_LDS_CAP = 64 * 1024;  // dynamic LDS per workgroup
 
+// Grid modes of the tiled kernels: one workgroup per tile; a persistent grid
+// whose workgroups prefetch their next tile; a persistent grid of
+// wave-specialised workgroups (a loader wave stages the next tile into a
+// second LDS buffer while four compute waves interpolate).
+enum { GRID_FULL = 0, GRID_PERSISTENT = 1, GRID_WS = 2 };
+
 // One tile configuration: runs of PX consecutive pixels per lane, TXT lanes
 // per tile row, CPT runs per lane, RPT rows per lane (tile = TXT*PX*CPT wide,
-// (256/TXT)*RPT high); persistent or one-tile-per-block grid.
+// (256/TXT)*RPT high), and the grid mode.
 struct TileCfg {
     int px, txt, cpt, rpt;
-    bool persistent;
+    int grid;
 };
 
 // Compiled tile configurations (PX, TXT, CPT, RPT) per operation: the
@@ -33,6 +39,8 @@ hipError_t launch_tiled_cfg(int op, int c, kr_dtype dt, const TileCfg &cfg, cons
                             hipStream_t s, bool &fits);
 
 int device_cus();
+// Resident workgroups per CU of a kernel at a dynamic LDS size (cached).
+int blocks_per_cu(const void *kernel, size_t lds, int threads = 256);
 int persistent_grid(int ntiles, int per_cu);
 TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th);
 TileGeom tile_geom(const ImageJob &j, int op, int tw, int th);

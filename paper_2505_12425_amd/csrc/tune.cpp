@@ -49,35 +49,52 @@ bool known_cfg(const TuneKey &k, const TileCfg &c)
         (k.batch != 0 && k.batch != 1))
         return false;
     for (const TileCfg &x : k.batch ? batch_candidates(k.op) : image_candidates(k.op))
-        if (x.px == c.px && x.txt == c.txt && x.cpt == c.cpt && x.rpt == c.rpt && x.persistent == c.persistent)
+        if (x.px == c.px && x.txt == c.txt && x.cpt == c.cpt && x.rpt == c.rpt && x.grid == c.grid)
             return true;
     return false;
 }
 
-// Parse the text form (one entry per line, '#' comments).  All or nothing:
-// a malformed line or a configuration the library was not compiled with rejects the
-// whole text.
-bool parse_table(const std::string &text, std::vector<std::pair<TuneKey, TileCfg>> &out)
+// Parse the text form (one entry per line, '#' comments).  The first entry
+// line is the build key, "key <arch> <kernel-source hash>"; a table whose key
+// differs from this library's (another GPU architecture, or kernels edited
+// since it was measured) is stale: TABLE_STALE, nothing taken.  All or
+// nothing otherwise: a malformed line or a configuration the library was not
+// compiled with rejects the whole text (TABLE_BAD).
+enum { TABLE_OK, TABLE_BAD, TABLE_STALE };
+
+int parse_table(const std::string &text, std::vector<std::pair<TuneKey, TileCfg>> &out)
 {
     std::istringstream in(text);
     std::string line;
+    bool keyed = false;
     while (std::getline(in, line)) {
         const size_t first = line.find_first_not_of(" \t\r");
         if (first == std::string::npos || line[first] == '#')
             continue;
+        if (!keyed) {
+            char arch[32], sha[32];
+            int used = 0;
+            if (std::sscanf(line.c_str(), " key %31s %31s %n", arch, sha, &used) != 2 ||
+                line.find_first_not_of(" \t\r", used) != std::string::npos)
+                return TABLE_BAD;
+            if (std::string(arch) + " " + sha != tune_build_key())
+                return TABLE_STALE;
+            keyed = true;
+            continue;
+        }
         TuneKey k;
         TileCfg c;
         int pers = 0, used = 0;
         if (std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %d %d %d %d %n", &k.op, &k.c, &k.f32, &k.batch,
                         &k.sclass, &k.zclass, &c.px, &c.txt, &c.cpt, &c.rpt, &pers, &used) != 11 ||
-            line.find_first_not_of(" \t\r", used) != std::string::npos || (pers != 0 && pers != 1))
-            return false;
-        c.persistent = pers != 0;
+            line.find_first_not_of(" \t\r", used) != std::string::npos || pers < GRID_FULL || pers > GRID_WS)
+            return TABLE_BAD;
+        c.grid = pers;
         if (!known_cfg(k, c))
-            return false;
+            return TABLE_BAD;
         out.push_back({k, c});
     }
-    return true;
+    return keyed || out.empty() ? TABLE_OK : TABLE_BAD;
 }
 
 void load_env_locked()
@@ -94,8 +111,9 @@ void load_env_locked()
     std::stringstream ss;
     ss << f.rdbuf();
     std::vector<std::pair<TuneKey, TileCfg>> v;
-    if (!parse_table(ss.str(), v)) {
-        std::fprintf(stderr, "libkr: ignoring malformed tuning cache %s\n", path);
+    const int r = parse_table(ss.str(), v);
+    if (r != TABLE_OK) {
+        std::fprintf(stderr, "libkr: ignoring %s tuning cache %s\n", r == TABLE_STALE ? "stale" : "malformed", path);
         return;
     }
     for (const auto &kv : v)
@@ -161,35 +179,48 @@ std::string tune_key_string(const TuneKey &k)
 std::string tune_cfg_string(const TileCfg &c)
 {
     char b[96];
-    std::snprintf(b, sizeof b, "%dx%dx%dx%d %s", c.px, c.txt, c.cpt, c.rpt, c.persistent ? "persistent" : "full");
+    std::snprintf(b, sizeof b, "%dx%dx%dx%d %s", c.px, c.txt, c.cpt, c.rpt, c.grid == GRID_WS ? "ws" : (c.grid == GRID_PERSISTENT ? "persistent" : "full"));
     return b;
 }
 
 std::string tune_dump()
 {
     std::lock_guard<std::mutex> g(g_mu);
+    load_env_locked();
     std::ostringstream o;
-    o << "# op c f32 batch sclass zclass px txt cpt rpt persistent\n";
+    o << "# op c f32 batch sclass zclass px txt cpt rpt grid\n";
+    o << "key " << tune_build_key() << '\n';
     for (const auto &kv : g_table) {
         const auto &k = kv.first;
         const TileCfg &c = kv.second;
         o << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
           << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << c.px << ' ' << c.txt << ' ' << c.cpt << ' ' << c.rpt
-          << ' ' << (c.persistent ? 1 : 0) << '\n';
+          << ' ' << c.grid << '\n';
     }
     return o.str();
 }
 
-bool tune_load_text(const std::string &text)
+int tune_load_text(const std::string &text)
 {
     std::vector<std::pair<TuneKey, TileCfg>> v;
-    if (!parse_table(text, v))
-        return false;
+    const int r = parse_table(text, v);
+    if (r != TABLE_OK)
+        return r == TABLE_STALE ? 2 : 1;
     std::lock_guard<std::mutex> g(g_mu);
     g_loaded = true;
     for (const auto &kv : v)
         g_table[tup(kv.first)] = kv.second;
-    return true;
+    return 0;
+}
+
+// The build this library's tables belong to: the GPU architecture it was
+// compiled for and the hash of its kernel sources (passed by the build).
+const char *tune_build_key()
+{
+#ifndef KR_SOURCE_SHA
+#define KR_SOURCE_SHA "unknown"
+#endif
+    return "gfx950 " KR_SOURCE_SHA;
 }
 
 hipError_t time_launches(const std::function<hipError_t()> &launch, int reps, void *scrub, size_t scrub_bytes,
@@ -243,8 +274,9 @@ std::vector<TileCfg> image_candidates(int op)
 {
     std::vector<TileCfg> v;
 #define KR_ADD(PX, TXT, CPT, RPT)                   \
-    v.push_back(TileCfg{PX, TXT, CPT, RPT, true});  \
-    v.push_back(TileCfg{PX, TXT, CPT, RPT, false});
+    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_PERSISTENT});  \
+    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_FULL});        \
+    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_WS});
     if (op != OP_RESIZE) {
         KR_WARP_CFGS(KR_ADD)
     } else {
@@ -257,7 +289,9 @@ std::vector<TileCfg> image_candidates(int op)
 std::vector<TileCfg> batch_candidates(int op)
 {
     std::vector<TileCfg> v;
-#define KR_ADD(PX, TXT, CPT, RPT) v.push_back(TileCfg{PX, TXT, CPT, RPT, false});
+#define KR_ADD(PX, TXT, CPT, RPT)                            \
+    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_FULL});     \
+    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_PERSISTENT});
     if (op == OP_WARP) {
         KR_BATCH_WARP_CFGS(KR_ADD)
     } else {

@@ -28,10 +28,14 @@ void tune_clear();
 std::string tune_key_string(const TuneKey &k);
 std::string tune_cfg_string(const TileCfg &c);
 std::string tune_dump();
-bool tune_load_text(const std::string &text);
+// 0: merged; 1: malformed (table unchanged); 2: made for another build
+// (architecture or kernel sources differ; table unchanged).
+int tune_load_text(const std::string &text);
+// "<arch> <kernel-source hash>" of this library.
+const char *tune_build_key();
 
 // Every compiled configuration of an operation (single image: both grid
-// modes; batch: one-tile-per-block grids).
+// modes; batch: one-tile-per-block and persistent grids).
 std::vector<TileCfg> image_candidates(int op);
 std::vector<TileCfg> batch_candidates(int op);
 

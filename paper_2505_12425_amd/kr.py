@@ -75,6 +75,10 @@ def lib():
     L.kr_resize_nearest.restype = i
     L.kr_warp_perspective.argtypes = [vp, i, i, i, i, vp, i, i, i, dp, i, i, f, npp, vp]
     L.kr_warp_perspective.restype = i
+    L.kr_resize_bilinear_gray.argtypes = [vp, i, i, ctypes.c_size_t, vp, i, i, i, i, f, npp, vp]
+    L.kr_resize_bilinear_gray.restype = i
+    L.kr_warp_affine_gray.argtypes = [vp, i, i, ctypes.c_size_t, vp, i, i, i, dp, i, i, f, npp, vp]
+    L.kr_warp_affine_gray.restype = i
     sz_ = ctypes.c_size_t
     L.kr_resize_bilinear_view.argtypes = [vp, i, i, sz_, i, i, vp, i, i, i, i, f, npp, vp]
     L.kr_resize_bilinear_view.restype = i
@@ -135,6 +139,8 @@ def lib():
         L.kr_autotune_load.restype = i
         L.kr_autotune_clear.argtypes = []
         L.kr_autotune_clear.restype = None
+        L.kr_build_key.argtypes = []
+        L.kr_build_key.restype = cp
     _lib = L
     return L
 
@@ -289,6 +295,29 @@ def warp_affine(src, dst, m, inverse: bool = False, border: int = CONSTANT, bord
         check(lib().kr_warp_affine_view(sp, sh, sw, pitch, c, st, *args))
     else:
         check(lib().kr_warp_affine(sp, sh, sw, c, st, *args))
+
+
+def resize_gray(src, dst, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
+                stream=None) -> None:
+    """kr_resize_bilinear_gray: RGB u8 source (contiguous or a view) -> one
+    gray channel (HxWx1 u8 or f32) in one pass."""
+    sp, sh, sw, pitch, c, st = _source(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if c != 3 or st != U8 or dc != 1:
+        raise ValueError("resize_gray takes an RGB u8 source and a one-channel destination")
+    check(lib().kr_resize_bilinear_gray(sp, sh, sw, pitch, dp_, dh, dw, dt, border, float(border_value),
+                                        _normalize(mean, std, 1), _stream(stream)))
+
+
+def warp_affine_gray(src, dst, m, inverse: bool = False, border: int = CONSTANT, border_value: float = 0.0,
+                     mean=None, std=None, stream=None) -> None:
+    """kr_warp_affine_gray: RGB u8 source -> one gray channel, in one pass."""
+    sp, sh, sw, pitch, c, st = _source(src)
+    dp_, dh, dw, dc, dt = _image(dst)
+    if c != 3 or st != U8 or dc != 1:
+        raise ValueError("warp_affine_gray takes an RGB u8 source and a one-channel destination")
+    check(lib().kr_warp_affine_gray(sp, sh, sw, pitch, dp_, dh, dw, dt, _m6(m), WARP_INVERSE_MAP if inverse else 0,
+                                    border, float(border_value), _normalize(mean, std, 1), _stream(stream)))
 
 
 def _m9(m):
@@ -471,6 +500,11 @@ def autotune_load(text: str) -> None:
 
 def autotune_clear() -> None:
     lib().kr_autotune_clear()
+
+
+def build_key() -> str:
+    """"<arch> <kernel-source hash>" of the loaded library (kr_build_key)."""
+    return lib().kr_build_key().decode()
 
 
 class BatchPlan:

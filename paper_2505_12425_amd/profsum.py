@@ -20,7 +20,6 @@ from __future__ import annotations
 import argparse
 import csv
 import glob
-import hashlib
 import json
 import os
 import re
@@ -31,14 +30,10 @@ CSRC = os.path.join(PKG, "csrc")
 
 
 def kernel_source_sha() -> str:
-    """Hash of every kernel and host source file of libkr."""
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of every kernel and host source file of libkr (the same hash the
+    library carries in its build key)."""
+    from .build import source_sha
+    return source_sha()
 
 
 _TPL = re.compile(r"kr::k_(tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"

@@ -152,6 +152,25 @@ static void test_launch_failure_requeues()
     CHECK((ex.launched_ids.back() == std::vector<uint64_t>{0, 1, 2}));
 }
 
+// The budget is the server's own memory: the output blocks it allocates.
+// Sources are the caller's resident buffers, which the server neither copies
+// nor allocates, so their size does not enter admission.
+static void test_admission_counts_outputs_only()
+{
+    FakeExec ex(1);
+    Scheduler<FakeExec> s(ex, 4096, 1, 8);
+    Request big_src = req(0, 1024);
+    big_src.sh = 2160;
+    big_src.sw = 3840;  // a 24.9 MB source, far above the 4 KiB budget
+    CHECK(s.submit(big_src));
+    CHECK(s.submit(req(1, 3072)));
+    CHECK(s.submit(req(2, 256)));  // over the budget once 0 and 1 hold it
+    std::vector<Completion> out;
+    CHECK(s.step(0, out));
+    CHECK((ex.launched_ids[0] == std::vector<uint64_t>{0, 1}));
+    CHECK(s.arena().used() == 4096 && s.queued() == 1);
+}
+
 static void test_random_simulation()
 {
     std::mt19937 rng(1234);
@@ -206,6 +225,7 @@ int main()
     test_fifo_budget_and_limits();
     test_head_of_line_waits();
     test_launch_failure_requeues();
+    test_admission_counts_outputs_only();
     test_random_simulation();
     std::printf("OK\n");
     return 0;

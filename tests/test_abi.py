@@ -218,12 +218,15 @@ def test_server_config_validation():
 
 def test_autotune_table_roundtrip_and_validation():
     kr.autotune_clear()
-    assert kr.autotune_save().strip() == "# op c f32 batch sclass zclass px txt cpt rpt persistent"
-    good = ("# comment\n"
+    key = "key " + kr.build_key()
+    header = "# op c f32 batch sclass zclass px txt cpt rpt grid\n" + key + "\n"
+    assert kr.autotune_save() == header
+    good = ("# comment\n" + key + "\n"
             "2 3 0 0 1 11 4 16 1 2 0\n"
             "1 3 0 0 0 11 4 16 1 4 1\n"
             "0 4 1 0 -4 10 1 64 2 4 0\n"
-            "1 3 1 1 2 13 4 8 1 1 0\n")
+            "1 3 1 1 2 13 4 8 1 1 0\n"
+            "1 3 1 0 1 11 1 64 1 8 2\n")
     kr.autotune_load(good)
     lines = [ln for ln in kr.autotune_save().splitlines() if not ln.startswith("#")]
     assert sorted(lines) == sorted(ln for ln in good.splitlines() if not ln.startswith("#"))
@@ -232,20 +235,53 @@ def test_autotune_table_roundtrip_and_validation():
                 "1 3 0 0 0 11 4 16 1 4 1 9\n",       # trailing field
                 "1 3 0 0 0 11 4 12 1 4 1\n",         # no such configuration
                 "1 3 0 1 0 11 4 16 1 4 1\n",         # batches have no persistent grids
+                "1 3 0 0 0 11 4 16 1 4 3\n",         # no such grid mode
                 "3 3 0 0 0 11 4 16 1 4 1\n",         # unknown op
                 "2 3 0 1 0 11 4 16 1 2 0\n",         # perspective warps have no batched form
                 "1 2 0 0 0 11 4 16 1 4 1\n",         # channel count without configurations
                 "0 3 0 0 0 11 1 64 2 4 0\nbogus\n"]:  # one bad line rejects the whole text
         with pytest.raises(kr.KrError) as e:
-            kr.autotune_load(bad)
+            kr.autotune_load(key + "\n" + bad)
         assert e.value.status == kr.ERR_INVALID_ARGUMENT
+        assert kr.autotune_save() == before
+    # no build key: rejected as malformed
+    with pytest.raises(kr.KrError) as e:
+        kr.autotune_load("1 3 0 0 0 11 4 16 1 4 1\n")
+    assert e.value.status == kr.ERR_INVALID_ARGUMENT
+    # a table measured on another build (kernel sources or architecture) is stale: ignored
+    arch, sha = kr.build_key().split()
+    for stale in [f"key {arch} {'0' * 16}", f"key gfx942 {sha}"]:
+        with pytest.raises(kr.KrError) as e:
+            kr.autotune_load(stale + "\n1 3 0 0 0 11 4 16 1 4 1\n")
+        assert e.value.status == kr.ERR_UNSUPPORTED
         assert kr.autotune_save() == before
     # truncated save: NUL-terminated prefix, full length reported
     buf = ctypes.create_string_buffer(10)
     need = kr.lib().kr_autotune_save(buf, 10)
     assert need == len(before) + 1 and buf.value.decode() == before[:9]
     kr.autotune_clear()
-    assert kr.autotune_save() == "# op c f32 batch sclass zclass px txt cpt rpt persistent\n"
+    assert kr.autotune_save() == header
+
+
+def test_build_key_names_arch_and_kernel_sources():
+    from paper_2505_12425_amd.build import source_sha
+    assert kr.build_key() == "gfx950 " + source_sha()
+
+
+def test_stale_tuning_cache_file_is_ignored(tmp_path):
+    """A KR_AUTOTUNE_CACHE file from another build is reported and ignored
+    (checked in a fresh process: the file is read on first use)."""
+    import subprocess
+    import sys
+    f = tmp_path / "stale.txt"
+    f.write_text("key gfx950 " + "f" * 16 + "\n1 3 0 0 0 11 4 16 1 4 1\n")
+    code = ("import sys; sys.path.insert(0, %r); from paper_2505_12425_amd import kr; "
+            "print(repr(kr.autotune_save()))" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], env={**os.environ, "KR_AUTOTUNE_CACHE": str(f)},
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "stale tuning cache" in r.stderr
+    assert "1 3 0 0 0 11 4 16 1 4 1" not in r.stdout
 
 
 def test_autotune_validation():

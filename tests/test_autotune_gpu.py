@@ -42,7 +42,7 @@ def clean_table():
 def tuned_keys(batch):
     out = []
     for ln in kr.autotune_save().splitlines():
-        if ln.startswith("#"):
+        if ln.startswith("#") or ln.startswith("key "):
             continue
         v = ln.split()
         if int(v[3]) == batch:
@@ -88,11 +88,11 @@ def test_every_image_config_bit_exact(op, out):
     assert np.array_equal(tuned, default)
     (key,) = tuned_keys(0)
     for px, txt, cpt, rpt in compiled_cfgs("KR_WARP_CFGS" if op == "warp" else "KR_RESIZE_CFGS"):
-        for pers in (0, 1):
+        for grid in (0, 1, 2):  # one workgroup per tile, persistent, wave-specialised
             kr.autotune_clear()
-            kr.autotune_load(f"{key} {px} {txt} {cpt} {rpt} {pers}\n")
+            kr.autotune_load(f"key {kr.build_key()}\n{key} {px} {txt} {cpt} {rpt} {grid}\n")
             got = run()
-            assert np.array_equal(got, default), f"{op} {out} config {px}x{txt}x{cpt}x{rpt} pers={pers}"
+            assert np.array_equal(got, default), f"{op} {out} config {px}x{txt}x{cpt}x{rpt} grid={grid}"
 
 
 @pytest.mark.parametrize("out", ["u8", "f32"])
@@ -125,12 +125,13 @@ def test_every_batch_config_bit_exact(out):
     for key in keys:
         op = int(key.split()[0])
         for px, txt, cpt, rpt in compiled_cfgs("KR_BATCH_WARP_CFGS" if op == 1 else "KR_BATCH_RESIZE_CFGS"):
-            kr.autotune_clear()
-            kr.autotune_load(f"{key} {px} {txt} {cpt} {rpt} 0\n")
-            for sp in specs:
-                sp["dst"].zero_()
-            kr.resize_batch(specs, border=kr.REPLICATE)
-            torch.cuda.synchronize()
-            for k, sp in enumerate(specs):
-                assert np.array_equal(sp["dst"].cpu().numpy(), default[k]), \
-                    f"batch op {op} config {px}x{txt}x{cpt}x{rpt} item {k}"
+            for grid in (0, 1):  # one workgroup per tile, persistent
+                kr.autotune_clear()
+                kr.autotune_load(f"key {kr.build_key()}\n{key} {px} {txt} {cpt} {rpt} {grid}\n")
+                for sp in specs:
+                    sp["dst"].zero_()
+                kr.resize_batch(specs, border=kr.REPLICATE)
+                torch.cuda.synchronize()
+                for k, sp in enumerate(specs):
+                    assert np.array_equal(sp["dst"].cpu().numpy(), default[k]), \
+                        f"batch op {op} config {px}x{txt}x{cpt}x{rpt} grid {grid} item {k}"

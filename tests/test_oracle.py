@@ -448,6 +448,71 @@ def test_gray_matches_integer_and_float_definitions():
     assert np.allclose(g, src.astype(np.float64) @ np.array([0.299, 0.587, 0.114]), rtol=0, atol=1e-9)
 
 
+def test_gray_u8_within_bound_of_exact_bt601_over_all_inputs():
+    """Every one of the 2^24 RGB triples, against the exact BT.601 luma
+    0.299 R + 0.587 G + 0.114 B (an independent bound, not the integer
+    formula restated): the 14-bit weights are each within 0.5/16384 of the
+    exact ones, so the result is within 0.5 + 255 * 1.5 / 16384 < 0.524 of
+    the exact value.  A swapped, truncated or dropped weight breaks the
+    bound by far (swapping R and B is off by up to 47)."""
+    v = np.arange(1 << 24, dtype=np.uint32)
+    img = np.stack([(v >> 16) & 255, (v >> 8) & 255, v & 255], axis=-1).astype(np.uint8).reshape(4096, 4096, 3)
+    g = oracle.rgb_to_gray(img, threads=8)[..., 0].astype(np.float64)
+    q = img.astype(np.float64)
+    exact = 0.299 * q[..., 0] + 0.587 * q[..., 1] + 0.114 * q[..., 2]
+    err = np.abs(g - exact)
+    assert err.max() < 0.524
+    # and the rounding is to nearest: the bound is attained only near halves
+    assert np.all((err <= 0.5) | (np.abs(exact - np.floor(exact) - 0.5) < 0.024))
+
+
+# ---------------------------------------------------------------- fused RGB -> gray
+GRAY_W = np.array([0.299, 0.587, 0.114])
+
+
+@pytest.mark.parametrize("shape", [(31, 47, 17, 23), (20, 30, 45, 61), (64, 64, 32, 32)])
+def test_resize_gray_on_grey_images_is_the_one_channel_resize(shape):
+    """R = G = B: every channel resizes alike and gray(v, v, v) = v, so the
+    fused result is the one-channel resize, bit for bit (an independent
+    path through the oracle)."""
+    h, w, dh, dw = shape
+    g = wl.uniform_u8(h, w, 1, seed=h + w)
+    rgb = np.repeat(g, 3, axis=-1)
+    assert np.array_equal(oracle.resize_gray(rgb, dh, dw), oracle.resize(g, dh, dw))
+    m = wl.affine_compose(h, w, 17.0, 0.9, 0.1, 2.5, -1.5)
+    assert np.array_equal(oracle.warp_gray(rgb, m, dh, dw, bval=77.0),
+                          oracle.warp(g, m, dh, dw, bval=77.0))
+
+
+@pytest.mark.parametrize("border,bval", [(oracle.REPLICATE, 0.0), (oracle.CONSTANT, 40.0)])
+def test_gray_commutes_with_resampling_f64(border, bval):
+    """Both maps are linear (and the gray weights sum to one, so a constant
+    border stays itself): gray after resampling equals resampling the gray
+    image (here held as f32, so within its rounding: 255 * 2^-24 < 3e-5)."""
+    img = wl.uniform_u8(29, 37, 3, seed=7)
+    gray = (img.astype(np.float64) @ GRAY_W)[..., None].astype(np.float32)
+    got = oracle.resize_gray(img, 41, 19, "f64", border, bval)
+    assert np.allclose(got, oracle.resize(gray, 41, 19, "f64", border, bval), rtol=0, atol=3e-5)
+    m = wl.affine_compose(29, 37, -23.0, 1.2, -0.1, 3.0, 4.0)
+    got = oracle.warp_gray(img, m, 33, 35, "f64", border=border, bval=bval)
+    assert np.allclose(got, oracle.warp(gray, m, 33, 35, "f64", border=border, bval=bval), rtol=0, atol=3e-5)
+    n = oracle.warp_gray(img, m, 33, 35, "f64", border=border, bval=bval, mean=[0.45], std=[0.25])
+    assert np.allclose(n, (got / 255.0 - 0.45) / 0.25, rtol=0, atol=1e-12)
+
+
+def test_gray_u8_within_two_roundings_of_exact():
+    """u8: each channel is within 1/2 of its exact interpolated value, and the
+    14-bit gray is within 0.524 of the exact BT.601 combination of its
+    inputs (the all-inputs bound above): within 1.03 of the exact gray of
+    the exact interpolation.  A swapped or dropped channel is far off."""
+    img = wl.uniform_u8(40, 56, 3, seed=3)
+    exact = oracle.resize(img, 29, 31, "f64") @ GRAY_W
+    assert np.abs(oracle.resize_gray(img, 29, 31)[..., 0] - exact).max() < 1.03
+    m = wl.affine_compose(40, 56, 31.0, 1.1, 0.0, -2.0, 5.0)
+    exact = oracle.warp(img, m, 40, 56, "f64") @ GRAY_W
+    assert np.abs(oracle.warp_gray(img, m, 40, 56)[..., 0] - exact).max() < 1.03
+
+
 # ---------------------------------------------------------------- perspective warp
 def test_homography_inverse():
     assert np.array_equal(oracle.invert_homography([2, 0, 0, 0, 4, 0, 0, 0, 1]), [0.5, 0, 0, 0, 0.25, 0, 0, 0, 1])
