@@ -52,6 +52,8 @@ struct TiledJob {
     double rden_x;    // resize: 1 / (2 dst_w), rounded (exact quotients by correction)
     double rden_y;    // resize: 1 / (2 dst_h), rounded
     int op;           // OP_RESIZE or OP_WARP
+    int rows_contig;  // resize: stage the tile's source rows once each (vertical ratio <= 2, every row
+                      // of the span is a tap row); else two LDS rows per output row
     int tiles_x;      // output tiles per row
     int ntiles;       // output tiles in the image
     int first_tile;   // index of the image's first tile in a batch work-list
@@ -576,7 +578,8 @@ struct TileGeom {
 struct Plan {
     int ox0, oy0, ox1, oy1;  // output pixels covered (inclusive)
     int bx0, bw;             // box columns [bx0, bx0 + bw)
-    int by0, nslots;         // warp: slot s = source row by0 + s; resize: two slots per output row
+    int by0, nslots;         // slot s = source row by0 + s (warps; resizes with rows_contig),
+                             // else (resizes) two slots per output row
     int cx0, cx1, ng;        // in-image box columns; 16-pixel groups per slot (upper bound)
     bool inside;             // every tap of the tile lies inside the image
     bool direct;             // box exceeds the LDS budget: per-pixel evaluation
@@ -637,8 +640,13 @@ __device__ __forceinline__ Plan make_plan(const TiledJob &t, int tile, const Til
         y0min = __builtin_amdgcn_readlane(v, 2);
         y0max = __builtin_amdgcn_readlane(v, 3);
         p.inside = x0min >= 0 && x0max + 1 <= W - 1 && y0min >= 0 && y0max + 1 <= H - 1;
-        p.by0 = 0;
-        p.nslots = 2 * (p.oy1 - p.oy0 + 1);
+        if (t.rows_contig) {
+            p.by0 = y0min;
+            p.nslots = y0max + 2 - y0min;
+        } else {
+            p.by0 = 0;
+            p.nslots = 2 * (p.oy1 - p.oy0 + 1);
+        }
     } else if constexpr (OP == OP_PERSP) {
         // Tap box from the four corners (lane q takes corner q).  Where w > 0
         // at the corners it is positive over the whole tile, whose image is
@@ -732,7 +740,7 @@ __device__ __forceinline__ int slot_row(const TiledJob &t, const Plan &p, int s)
     const ImageJob &j = t.j;
     int y;
     if constexpr (OP == OP_RESIZE) {
-        y = resize_i0_r(p.oy0 + (s >> 1), j.sh, j.dh, t.rden_y) + (s & 1);
+        y = t.rows_contig ? p.by0 + s : resize_i0_r(p.oy0 + (s >> 1), j.sh, j.dh, t.rden_y) + (s & 1);
     } else {
         y = p.by0 + s;
     }
@@ -751,15 +759,21 @@ template <int C, int MAXIT> struct Prefetch {
     int p0[MAXIT];   // linear index of the group's first pixel
 };
 
-// Locate work item k: its LDS destination and first pixel, or false.
+// Work items of a tile's staging: each slot's groups in runs of four, so that
+// four consecutive lanes read 192 (RGB) or 256 (RGBA) contiguous source
+// bytes, and consecutive runs of lanes take consecutive slots (with a pitch of
+// 17 (mod 32) their LDS writes start on different banks).
+__device__ __forceinline__ int staging_items(const Plan &p) { return p.nslots * ((p.ng + 3) & ~3); }
+
+// Locate work item k: its slot s, group index gi within the slot's row, LDS
+// destination and first pixel; false if the slot's row has no such group.
 template <int OP>
-__device__ __forceinline__ bool group_of(const TiledJob &t, const Plan &p, const TileGeom &G, int k, int &dst, int &p0)
+__device__ __forceinline__ bool group_of(const TiledJob &t, const Plan &p, const TileGeom &G, int k, int &dst, int &p0,
+                                         int &s, int &gi)
 {
-    // slot-major: consecutive lanes take the same group index of consecutive
-    // slots, so with a pitch of 17 (mod 32) their 16-dword writes start on
-    // different LDS banks
-    const int gi = udiv_small(k, p.nslots);
-    const int s = k - gi * p.nslots;
+    const int run = udiv_small(k >> 2, p.nslots);
+    s = (k >> 2) - run * p.nslots;
+    gi = 4 * run + (k & 3);
     const int rowbase = t.j.sk + slot_row<OP>(t, p, s) * t.j.sp;
     const int g = ((rowbase + p.cx0) >> 4) + gi;
     if (g > ((rowbase + p.cx1) >> 4))
@@ -824,13 +838,13 @@ __device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const
 {
     const uint8_t *src = static_cast<const uint8_t *>(t.j.src);
     const int lo = t.j.sk, hi = src_end(t.j);
-    const int total = p.nslots * p.ng;
+    const int total = staging_items(p);
 #pragma unroll
     for (int it = 0; it < MAXIT; it++) {
         const int k = lt + it * NLT;
         pf.dst[it] = -1;
-        int dst, p0;
-        if (k < total && group_of<OP>(t, p, G, k, dst, p0)) {
+        int dst, p0, s, gi;
+        if (k < total && group_of<OP>(t, p, G, k, dst, p0, s, gi)) {
             pf.dst[it] = dst;
             pf.p0[it] = p0;
             if (p0 >= lo && p0 + 16 <= hi)
@@ -856,14 +870,14 @@ __device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const T
                 write_tail_group<C>(lds + pf.dst[it], src, pf.p0[it], lo, hi);
         }
     }
-    const int total = p.nslots * p.ng;
+    const int total = staging_items(p);
     for (int k0 = lt + MAXIT * NLT; k0 < total; k0 += MAXIT * NLT) {
 #pragma unroll
         for (int it = 0; it < MAXIT; it++) {
             const int k = k0 + it * NLT;
             pf.dst[it] = -1;
-            int dst, p0;
-            if (k < total && group_of<OP>(t, p, G, k, dst, p0)) {
+            int dst, p0, s, gi;
+            if (k < total && group_of<OP>(t, p, G, k, dst, p0, s, gi)) {
                 pf.dst[it] = dst;
                 pf.p0[it] = p0;
                 if (p0 >= lo && p0 + 16 <= hi)
@@ -993,6 +1007,14 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
     const bool aligned = layout_aligned<C, F32, L>(j.dw);
     const uint32_t sel = quad_selector(lane_id() & 3);
     const int x_end = p.ox1 + 1;
+    // u8 inside tiles: the round-half-even constant 1.5 * 2^52 less 2048
+    // times the box origin (an even whole number, so ties still go to the
+    // even neighbour, and the sum stays in [2^52, 2^53), where the spacing
+    // is 1) leaves rne(X) - 2048 (bx0 - KT_MARGIN) in the low word: its high
+    // bits are the LDS column, its low 11 bits the weight (a multiple of
+    // 2048 moved), with no subtraction per pixel.
+    const double rx = in_vgpr(6755399441055744.0 - 2048.0 * (double)(p.bx0 - KT_MARGIN));
+    const double ry = in_vgpr(6755399441055744.0 - 2048.0 * (double)p.by0);
     double xd[CPT][PX];
 #pragma unroll
     for (int c = 0; c < CPT; c++)
@@ -1026,17 +1048,27 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                             Y = clamp_scaled(Y, H);
                         }
                     }
-                    const int Nx = rne_i32(X), Ny = rne_i32(Y);
-                    const int x0 = Nx >> 11, y0 = Ny >> 11;
-                    uint32_t wx1 = (uint32_t)Nx & 2047u, wy1 = (uint32_t)Ny & 2047u;
-                    uint32_t wx0 = 2048u - wx1, wy0 = 2048u - wy1;
-                    uint32_t corr = 0;
-                    if (MASK)
-                        corr = mask_weights(x0, y0, W, H, wx0, wx1, wy0, wy1, (uint32_t)e.bval_i);
-                    const int a = __mul24(y0, pitch) + x0 - base;
                     uint32_t v[C];
-                    interp_u8<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0 | (wx1 << 16), wy0 << 2,
-                                 wy1 << 2, v);
+                    uint32_t corr = 0;
+                    if constexpr (!CLAMP && !PERSP) {
+                        const uint32_t Nx = (uint32_t)__builtin_bit_cast(uint64_t, X + rx);
+                        const uint32_t Ny = (uint32_t)__builtin_bit_cast(uint64_t, Y + ry);
+                        const uint32_t a = __umul24(Ny >> 11, (uint32_t)pitch) + (Nx >> 11);
+                        const uint32_t wy1_4 = (Ny << 2) & 8188u;
+                        // (2048 - w) | w << 16 = 2048 + 65535 w
+                        interp_u8<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1],
+                                     __umul24(Nx & 2047u, 65535u) + 2048u, 8192u - wy1_4, wy1_4, v);
+                    } else {
+                        const int Nx = rne_i32(X), Ny = rne_i32(Y);
+                        const int x0 = Nx >> 11, y0 = Ny >> 11;
+                        uint32_t wx1 = (uint32_t)Nx & 2047u, wy1 = (uint32_t)Ny & 2047u;
+                        uint32_t wx0 = 2048u - wx1, wy0 = 2048u - wy1;
+                        if (MASK)
+                            corr = mask_weights(x0, y0, W, H, wx0, wx1, wy0, wy1, (uint32_t)e.bval_i);
+                        const int a = __mul24(y0, pitch) + x0 - base;
+                        interp_u8<C>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0 | (wx1 << 16),
+                                     wy0 << 2, wy1 << 2, v);
+                    }
                     if (MASK) {
 #pragma unroll
                         for (int q = 0; q < C; q++)
@@ -1139,7 +1171,7 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
             break;
         const int y0 = (int)tab[2 * TW + rr];
         const uint32_t rw = tab[2 * TW + TH + rr];
-        const int s0 = (2 * rr) * pitch;
+        const int s0 = (t.rows_contig ? y0 - p.by0 : 2 * rr) * pitch;
         const bool vy0 = (unsigned)y0 < (unsigned)H, vy1 = (unsigned)(y0 + 1) < (unsigned)H;
 #pragma unroll
         for (int c = 0; c < CPT; c++) {
@@ -1504,84 +1536,6 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         __syncthreads();
         t = nt;
         p = np;
-    }
-}
-
-// Wave-specialised tile pipeline: the workgroup has KT_THREADS compute
-// threads (the lane layout L) plus one loader wave (threads KT_THREADS ..
-// KT_THREADS + 63), and two LDS buffers of buf_dwords each.  The loader wave
-// stages tile i into buffer i & 1 (loads, LDS writes, edge columns, resize
-// tables) and issues the first loads of tile i + 1; the compute waves
-// interpolate tile i and store it.  One barrier per tile: when both sides
-// reach barrier i, tile i is staged and tile i - 1 has been consumed, so the
-// loader may overwrite the buffer tile i - 1 used.
-//
-// Why: on this architecture one counter tracks a wave's outstanding loads and
-// stores together, so a wave that waits for its staging loads also waits for
-// every store it issued before them.  Here the compute waves issue no loads
-// (gather tiles aside) and never wait on their stores; the loader wave issues
-// no stores.  Every wave of the workgroup takes the same tile sequence and
-// computes the same tile plans, so both sides execute the same number of
-// barriers.
-template <int OP, int C, bool F32, class L, int MAXIT, typename NextJob>
-__device__ __forceinline__ void run_tiles_ws(const TileGeom &G, const Epilogue &e, uint32_t *lds, int buf_dwords,
-                                             NextJob next_job)
-{
-    constexpr int TW = L::TW;
-    constexpr int TH = L::TH;
-    TiledJob t;
-    int tile;
-    if (!next_job(t, tile))
-        return;
-    const bool cb = e.border == KR_BORDER_CONSTANT;
-    Plan p = make_plan<OP, TW, TH, F32>(t, tile, G, cb);
-    if (__builtin_amdgcn_readfirstlane((int)threadIdx.x) >= KT_THREADS) {
-        const int lt = lane_id();
-        Prefetch<C, MAXIT> pf;
-        if (!p.direct)
-            prefetch<OP, C, MAXIT, 64>(t, p, G, pf, lt);
-        for (int i = 0;; i++) {
-            uint32_t *buf = lds + (i & 1) * buf_dwords;
-            if (!p.direct)
-                commit<OP, C, MAXIT, 64>(t, p, G, pf, buf, lt);
-            if constexpr (OP == OP_RESIZE)
-                resize_tables<TW, TH, F32, 64>(t, p, G, buf, lt);
-            // the edge columns overwrite what the group writes above spilled
-            // there; one wave's LDS writes complete in order
-            if (needs_edge_fill(t, p, e))
-                fill_edge_columns<OP, C, 64>(t, p, G, buf, lt);
-            TiledJob nt;
-            int ntile;
-            const bool more = next_job(nt, ntile);
-            if (more) {
-                p = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
-                if (!p.direct)
-                    prefetch<OP, C, MAXIT, 64>(nt, p, G, pf, lt);
-                t = nt;
-            }
-            __syncthreads();
-            if (!more)
-                break;
-        }
-    } else {
-        for (int i = 0;; i++) {
-            __syncthreads();
-            const uint32_t *buf = lds + (i & 1) * buf_dwords;
-            if (p.blank)
-                fill_blank<C, F32, L>(t, p, e);
-            else if (p.direct)
-                compute_gather<OP, C, F32, L>(t, p, G, e, buf);
-            else if constexpr (OP == OP_RESIZE)
-                compute_resize<C, F32, L>(t, p, G, e, buf);
-            else
-                compute_warp<C, F32, L, OP == OP_PERSP>(t, p, G, e, buf);
-            TiledJob nt;
-            int ntile;
-            if (!next_job(nt, ntile))
-                break;
-            t = nt;
-            p = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
-        }
     }
 }
 

@@ -33,22 +33,6 @@ __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, 
     });
 }
 
-// Wave-specialised persistent grid: KT_THREADS compute threads plus one
-// loader wave; the dynamic LDS holds two buffers of buf_dwords each.
-template <int OP, int C, bool F32, int PX, int TXT, int CPT, int RPT, int MAXIT>
-__global__ __launch_bounds__(KT_THREADS + 64) void k_tiled_ws(TiledJob job, Epilogue e, TileGeom G, int buf_dwords)
-{
-    extern __shared__ uint32_t lds[];
-    TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
-    run_tiles_ws<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT>(G, e, lds, buf_dwords,
-                                                                     [&](TiledJob &t, int &tile) {
-        if (!seq.take(tile))
-            return false;
-        t = job;
-        return true;
-    });
-}
-
 int device_cus()
 {
     static std::atomic<int> cus[64];  // 0 = not queried yet (static storage starts zeroed)
@@ -110,6 +94,7 @@ TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th)
     t.rden_x = 1.0 / (2.0 * (double)j.dw);
     t.rden_y = 1.0 / (2.0 * (double)j.dh);
     t.op = op;
+    t.rows_contig = op == OP_RESIZE && (double)j.sh <= 2.0 * (double)j.dh;
     t.tiles_x = (j.dw + tw - 1) / tw;
     t.ntiles = t.tiles_x * ((j.dh + th - 1) / th);
     t.first_tile = 0;
@@ -262,9 +247,11 @@ TileGeom tile_geom(const ImageJob &j, int op, int tw, int th)
         G.rows = (int)std::fmin(std::ceil(ey) + 4.0, (double)j.sh + 6.0);
         G.pitch = bank_pitch(G.pitch);
     } else {
-        const double rx = (double)j.sw / (double)j.dw;
+        const double rx = (double)j.sw / (double)j.dw, ry = (double)j.sh / (double)j.dh;
         G.pitch = (int)std::fmin(std::ceil(rx * (tw - 1)) + 3.0, (double)j.sw + 4.0) + KT_SPILL;
-        G.rows = 2 * th;
+        // rows_contig (ry <= 2): the floors of tap rows a span ry (th - 1)
+        // apart differ by at most its ceiling, plus the second tap row
+        G.rows = ry <= 2.0 ? (int)std::fmin(2.0 * th, std::ceil(ry * (th - 1)) + 3.0) : 2 * th;
         G.pitch = bank_pitch(G.pitch);
     }
     return G;
@@ -299,20 +286,6 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
         G.rows = 0;
     }
     const size_t lds = tile_lds_bytes(G, TW, TH);
-    if (mode == GRID_WS) {
-        // two buffers, each a whole number of 16-byte rows apart
-        const int buf_dwords = (int)((lds / 4 + 3) & ~(size_t)3);
-        fits = 8 * (size_t)buf_dwords <= KT_LDS_CAP;
-        if (!fits)
-            return hipSuccess;
-        constexpr int MAXIT_WS = 4;  // groups in flight per loader lane
-        auto kern = k_tiled_ws<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_WS>;
-        const size_t bytes = 8 * (size_t)buf_dwords;
-        const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), bytes,
-                                                                 KT_THREADS + 64));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS + 64), bytes, s, t, e, G, buf_dwords);
-        return hipGetLastError();
-    }
     fits = lds <= KT_LDS_CAP;
     if (!fits)
         return hipSuccess;
@@ -345,7 +318,7 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 }
 
 // Tile shapes tried in order (the first whose LDS footprint fits is used).
-// KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent"|"ws" override the
+// KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent" override the
 // first choice.
 static int default_cfgs(int op, bool f32, TileCfg *out)
 {
@@ -355,8 +328,7 @@ static int default_cfgs(int op, bool f32, TileCfg *out)
     int force = -1;
     if (grid)
         force = std::strcmp(grid, "full") == 0 ? GRID_FULL
-                : std::strcmp(grid, "persistent") == 0 ? GRID_PERSISTENT
-                : std::strcmp(grid, "ws") == 0 ? GRID_WS : -1;
+                : std::strcmp(grid, "persistent") == 0 ? GRID_PERSISTENT : -1;
     int px = 0, txt = 0, cpt = 0, rpt = 0;
     if (tile && std::sscanf(tile, "%dx%dx%dx%d", &px, &txt, &cpt, &rpt) == 4)
         out[n++] = TileCfg{px, txt, cpt, rpt, force >= 0 ? force : GRID_PERSISTENT};

@@ -11,11 +11,9 @@ struct TileGeom;
 
 constexpr size_t KT_LDS_CAP = 64 * 1024;  // dynamic LDS per workgroup
 
-// Grid modes of the tiled kernels: one workgroup per tile; a persistent grid
-// whose workgroups prefetch their next tile; a persistent grid of
-// wave-specialised workgroups (a loader wave stages the next tile into a
-// second LDS buffer while four compute waves interpolate).
-enum { GRID_FULL = 0, GRID_PERSISTENT = 1, GRID_WS = 2 };
+// Grid modes of the tiled kernels: one workgroup per tile, or a persistent
+// grid whose workgroups prefetch their next tile.
+enum { GRID_FULL = 0, GRID_PERSISTENT = 1 };
 
 // One tile configuration: runs of PX consecutive pixels per lane, TXT lanes
 // per tile row, CPT runs per lane, RPT rows per lane (tile = TXT*PX*CPT wide,

@@ -87,7 +87,7 @@ int parse_table(const std::string &text, std::vector<std::pair<TuneKey, TileCfg>
         int pers = 0, used = 0;
         if (std::sscanf(line.c_str(), "%d %d %d %d %d %d %d %d %d %d %d %n", &k.op, &k.c, &k.f32, &k.batch,
                         &k.sclass, &k.zclass, &c.px, &c.txt, &c.cpt, &c.rpt, &pers, &used) != 11 ||
-            line.find_first_not_of(" \t\r", used) != std::string::npos || pers < GRID_FULL || pers > GRID_WS)
+            line.find_first_not_of(" \t\r", used) != std::string::npos || pers < GRID_FULL || pers > GRID_PERSISTENT)
             return TABLE_BAD;
         c.grid = pers;
         if (!known_cfg(k, c))
@@ -179,7 +179,7 @@ std::string tune_key_string(const TuneKey &k)
 std::string tune_cfg_string(const TileCfg &c)
 {
     char b[96];
-    std::snprintf(b, sizeof b, "%dx%dx%dx%d %s", c.px, c.txt, c.cpt, c.rpt, c.grid == GRID_WS ? "ws" : (c.grid == GRID_PERSISTENT ? "persistent" : "full"));
+    std::snprintf(b, sizeof b, "%dx%dx%dx%d %s", c.px, c.txt, c.cpt, c.rpt, c.grid == GRID_PERSISTENT ? "persistent" : "full");
     return b;
 }
 
@@ -275,8 +275,7 @@ std::vector<TileCfg> image_candidates(int op)
     std::vector<TileCfg> v;
 #define KR_ADD(PX, TXT, CPT, RPT)                   \
     v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_PERSISTENT});  \
-    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_FULL});        \
-    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_WS});
+    v.push_back(TileCfg{PX, TXT, CPT, RPT, GRID_FULL});
     if (op != OP_RESIZE) {
         KR_WARP_CFGS(KR_ADD)
     } else {

@@ -36,10 +36,10 @@ def kernel_source_sha() -> str:
     return source_sha()
 
 
-_TPL = re.compile(r"kr::k_(tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"
+_TPL = re.compile(r"kr::k_(tiled_ws|tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"
                   r"(?:, (?:true|false))?>")
 _OPS = {"0": "resize", "1": "warp", "2": "perspective"}
-_POINT = re.compile(r"kr::(?:\(anonymous namespace\)::)?k_(nearest|flip_u8|flip_f32|gray|half)<([^>]*)>")
+_POINT = re.compile(r"kr::(?:\(anonymous namespace\)::)?k_(nearest|flip_u8|flip_f32|gray|half|permute)<([^>]*)>")
 
 
 def _short(name: str) -> str:
@@ -52,7 +52,7 @@ def label(name: str) -> str:
     if m:
         kind, op, c, f32, px, txt, cpt, rpt = m.groups()
         dt = "f32" if f32 == "true" else "u8"
-        pre = "batch_" if kind == "batch" else ""
+        pre = {"batch": "batch_", "tiled_ws": "ws_"}.get(kind, "")
         return f"{pre}{_OPS[op]}_{dt} c{c} {px}x{txt}x{cpt}x{rpt}"
     if "k_copy" in name:
         return "copy"
@@ -71,6 +71,8 @@ def label(name: str) -> str:
 
 def _point_key(kind: str, args: str) -> str | None:
     a = [t.strip() for t in args.split(",")]
+    if kind == "permute":  # <C, F32>
+        return None if a[0] != "3" else ("permute_f32" if a[1] == "true" else "permute_u8")
     if kind in ("flip_u8", "flip_f32"):
         return kind if a[0] == "3" else None
     if kind == "half":  # <C, DST_F32>
@@ -96,6 +98,53 @@ def bench_key(name: str) -> str | None:
     if c != "3":
         return None
     return ("batch_" if kind == "batch" else "") + _OPS[op] + ("_f32" if f32 == "true" else "_u8")
+
+
+def overlap(dir_: str, out: str, cmd: str) -> dict:
+    """Concurrency of kernel executions across hardware queues, from a
+    rocprofv3 kernel trace: how many dispatches overlap in time with a
+    dispatch of another queue, the summed kernel time over the time any
+    kernel runs (mean concurrency), and the most kernels running at once."""
+    path = _one(os.path.join(dir_, "**", "*kernel_trace.csv"))
+    rows = list(csv.DictReader(open(path)))
+    qcol = "Stream_Id" if rows and "Stream_Id" in rows[0] and any(r["Stream_Id"] not in ("", "0") for r in rows) \
+        else "Queue_Id"
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r[qcol], label(r["Kernel_Name"])) for r in rows)
+    n = len(ev)
+    overl = [False] * n
+    active = []  # (end, queue, index) of dispatches still running
+    busy = total = 0
+    cur_end = -1
+    cur_start = 0
+    peak = 0
+    for i, (t0, t1, q, _) in enumerate(ev):
+        active = [a for a in active if a[0] > t0]
+        for a in active:
+            if a[1] != q:
+                overl[i] = True
+                overl[a[2]] = True
+        active.append((t1, q, i))
+        peak = max(peak, len(active))
+        total += t1 - t0
+        if t0 > cur_end:
+            busy += cur_end - cur_start if cur_end > 0 else 0
+            cur_start, cur_end = t0, t1
+        else:
+            cur_end = max(cur_end, t1)
+    busy += cur_end - cur_start if n else 0
+    queues = sorted({e[2] for e in ev})
+    res = {"dispatches": n, "queues": len(queues), "overlapping_another_queue": int(sum(overl)),
+           "kernel_time_ms": round(total / 1e6, 3), "busy_time_ms": round(busy / 1e6, 3),
+           "mean_concurrency": round(total / busy, 3) if busy else 0.0, "peak_concurrency": peak}
+    lines = ["# Kernel overlap across queues (rocprofv3 kernel trace)", "", "Command:", "", "```", cmd, "```", "",
+             f"Queues seen ({qcol}): {len(queues)}.", "",
+             "| dispatches | overlapping a dispatch of another queue | kernel time (ms) | time any kernel runs (ms) "
+             "| mean concurrency | peak concurrency |", "|---:|---:|---:|---:|---:|---:|",
+             f"| {n} | {res['overlapping_another_queue']} | {res['kernel_time_ms']} | {res['busy_time_ms']} "
+             f"| {res['mean_concurrency']} | {peak} |", ""]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return res
 
 
 def _one(pattern: str) -> str:
@@ -226,6 +275,10 @@ def main() -> None:
     s.add_argument("--dir", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--cmd", required=True)
+    o = sub.add_parser("overlap")
+    o.add_argument("--dir", required=True)
+    o.add_argument("--out", required=True)
+    o.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -238,6 +291,8 @@ def main() -> None:
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.dir, a.out, a.cmd)
+    elif a.what == "overlap":
+        print(json.dumps(overlap(a.dir, a.out, a.cmd)))
     else:
         traffic(a.fetch, a.write, a.copy_bytes, a.out, a.md, a.cmd_fetch, a.cmd_write,
                 a.only.split(",") if a.only else None)

@@ -226,7 +226,7 @@ def test_autotune_table_roundtrip_and_validation():
             "1 3 0 0 0 11 4 16 1 4 1\n"
             "0 4 1 0 -4 10 1 64 2 4 0\n"
             "1 3 1 1 2 13 4 8 1 1 0\n"
-            "1 3 1 0 1 11 1 64 1 8 2\n")
+            "1 3 1 0 1 11 1 64 1 8 1\n")
     kr.autotune_load(good)
     lines = [ln for ln in kr.autotune_save().splitlines() if not ln.startswith("#")]
     assert sorted(lines) == sorted(ln for ln in good.splitlines() if not ln.startswith("#"))
@@ -235,7 +235,7 @@ def test_autotune_table_roundtrip_and_validation():
                 "1 3 0 0 0 11 4 16 1 4 1 9\n",       # trailing field
                 "1 3 0 0 0 11 4 12 1 4 1\n",         # no such configuration
                 "1 3 0 1 0 11 4 16 1 4 1\n",         # batches have no persistent grids
-                "1 3 0 0 0 11 4 16 1 4 3\n",         # no such grid mode
+                "1 3 0 0 0 11 4 16 1 4 2\n",         # no such grid mode
                 "3 3 0 0 0 11 4 16 1 4 1\n",         # unknown op
                 "2 3 0 1 0 11 4 16 1 2 0\n",         # perspective warps have no batched form
                 "1 2 0 0 0 11 4 16 1 4 1\n",         # channel count without configurations

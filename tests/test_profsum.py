@@ -63,3 +63,23 @@ def test_traffic_calibration_and_grouping(tmp_path):
     assert k["nearest_up_f32"]["bytes_per_launch"] == (2 * 20 + 120) * 1024
     assert k["gray_u8"]["bytes_per_launch"] == (2 * 7 + 8) * 1024
     assert k["gray_u8"]["calibration"]["fetch_factor"] == 2.0
+
+
+def test_overlap_counts_concurrent_dispatches_of_other_queues(tmp_path):
+    import csv
+    rows = [("0", 100, 200, "kr::k_batch<1, 3, false, 4, 16, 1, 2, 3, false>(x)"),
+            ("1", 150, 260, "kr::k_batch<1, 3, false, 4, 16, 1, 2, 3, false>(x)"),
+            ("0", 300, 400, "kr::k_copy(x)"),          # alone
+            ("0", 500, 600, "kr::k_copy(x)"),
+            ("2", 550, 580, "kr::k_copy(x)"),
+            ("2", 590, 595, "kr::k_copy(x)")]          # same queue as the one before: still overlaps queue 0
+    with open(tmp_path / "r_kernel_trace.csv", "w") as f:
+        w = csv.writer(f)
+        w.writerow(["Queue_Id", "Start_Timestamp", "End_Timestamp", "Kernel_Name"])
+        w.writerows(rows)
+    r = profsum.overlap(str(tmp_path), str(tmp_path / "o.md"), "cmd")
+    assert r["dispatches"] == 6 and r["queues"] == 3
+    assert r["overlapping_another_queue"] == 5
+    assert r["peak_concurrency"] == 2
+    assert abs(r["mean_concurrency"] - 445 / 360) < 1e-3
+    assert profsum.label(rows[0][3]) == "batch_warp_u8 c3 4x16x1x2"
