@@ -600,6 +600,24 @@ def bench_ops(args, torch, kr, wl):
             return lambda s: kr.rgb_to_gray(s, out)
         return make
 
+    # a quarter turn: the permutation path of kr_warp_affine (no interpolation)
+    rot90 = np.array([[0.0, 1.0, 0.0], [-1.0, 0.0, big[1] - 1.0]])
+
+    def turn(src):
+        out = torch.empty((big[1], big[0], 3), dtype=torch.uint8, device="cuda")
+        return lambda s: kr.warp_affine(s, out, rot90)
+
+    m4k = wl.random_affine_4k(big[0], big[1], 0)
+
+    def fused(op, dt):
+        def make(src):
+            hw = small if op == "resize" else big
+            out = torch.empty(hw + (1,), dtype=dt, device="cuda")
+            if op == "resize":
+                return lambda s: kr.resize_gray(s, out)
+            return lambda s: kr.warp_affine_gray(s, out, m4k)
+        return make
+
     u8, f32 = torch.uint8, torch.float32
     cases = [  # name, source size, output size, output bytes/px, source dtype, launcher
         ("nearest_down_u8", big, small, 3, u8, nearest(small, u8)),
@@ -612,6 +630,10 @@ def bench_ops(args, torch, kr, wl):
         ("gray_f32", big, big, 4, u8, gray(f32)),
         ("perspective_u8", big, big, 3, u8, persp(u8)),
         ("perspective_f32", big, big, 12, u8, persp(f32)),
+        ("rot90_u8", big, (big[1], big[0]), 3, u8, turn),
+        ("resize_gray_u8", big, small, 1, u8, fused("resize", u8)),
+        ("resize_gray_f32", big, small, 4, u8, fused("resize", f32)),
+        ("warp_gray_u8", big, big, 1, u8, fused("warp", u8)),
     ]
     for name, (h, w), (dh, dw), obytes, st, make in cases:
         img = wl.mixed_u8(h, w, 3, seed=0)
@@ -633,6 +655,10 @@ def bench_ops(args, torch, kr, wl):
         esize = 4 if st == torch.float32 else 1
         if name.startswith("nearest"):
             src_bytes = nearest_touched_bytes(h, w, dh, dw, esize=esize)
+        elif name.startswith("resize_gray"):
+            src_bytes = resize_touched_bytes(h, w, dh, dw)
+        elif name.startswith("warp_gray"):
+            src_bytes = warp_touched_bytes(h, w, dh, dw, kr.invert_affine(m4k.reshape(6)))
         elif name.startswith("perspective"):
             src_bytes = perspective_touched_bytes(h, w, dh, dw, _lib_invert_homography(kr, hm))
         else:
@@ -648,8 +674,8 @@ def bench_ops(args, torch, kr, wl):
     dom = max(kern, key=lambda n: kern[n]["avg_us"])
     k = kern[dom]
     return {
-        "metric": "output Gpixels/s (nearest resize 4K <-> 1080p, flip, RGB->gray and perspective warp at 4K, "
-                  "u8 and f32 outputs)",
+        "metric": "output Gpixels/s (nearest resize 4K <-> 1080p, flip, RGB->gray, perspective warp, a quarter "
+                  "turn and the fused resample+gray forms at 4K, u8 and f32 outputs)",
         "value": round(total_px / (total_ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(total_ms, 4),
         "config": {"workload": "ops: 3840x2160x3 u8 (f32 for the f32 flip) and 1920x1080x3 u8 sources, "
                                "one launch of each operator per step, cold sources", "px_per_step": total_px},
