@@ -667,7 +667,7 @@ def bench_ops(args, torch, kr, wl):
         gbps = alg / (ms * 1e-3) / 1e9
         kern[name] = {"avg_us": round(ms * 1e3, 3), "alg_bytes": alg, "GBps": round(gbps, 1),
                       "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(dh * dw / (ms * 1e-3) / 1e9, 2),
-                      "traffic": _traffic_from_profiles(name)}
+                      "traffic": _traffic_from_profiles({"rot90_u8": "permute_u8"}.get(name, name))}
         total_px += dh * dw
         total_ms += ms
         del srcs

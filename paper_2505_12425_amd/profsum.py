@@ -100,16 +100,8 @@ def bench_key(name: str) -> str | None:
     return ("batch_" if kind == "batch" else "") + _OPS[op] + ("_f32" if f32 == "true" else "_u8")
 
 
-def overlap(dir_: str, out: str, cmd: str) -> dict:
-    """Concurrency of kernel executions across hardware queues, from a
-    rocprofv3 kernel trace: how many dispatches overlap in time with a
-    dispatch of another queue, the summed kernel time over the time any
-    kernel runs (mean concurrency), and the most kernels running at once."""
-    path = _one(os.path.join(dir_, "**", "*kernel_trace.csv"))
-    rows = list(csv.DictReader(open(path)))
-    qcol = "Stream_Id" if rows and "Stream_Id" in rows[0] and any(r["Stream_Id"] not in ("", "0") for r in rows) \
-        else "Queue_Id"
-    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r[qcol], label(r["Kernel_Name"])) for r in rows)
+def _overlap_stats(ev) -> dict:
+    """Overlap figures of time-sorted dispatches (start, end, queue, label)."""
     n = len(ev)
     overl = [False] * n
     active = []  # (end, queue, index) of dispatches still running
@@ -132,18 +124,47 @@ def overlap(dir_: str, out: str, cmd: str) -> dict:
         else:
             cur_end = max(cur_end, t1)
     busy += cur_end - cur_start if n else 0
-    queues = sorted({e[2] for e in ev})
-    res = {"dispatches": n, "queues": len(queues), "overlapping_another_queue": int(sum(overl)),
-           "kernel_time_ms": round(total / 1e6, 3), "busy_time_ms": round(busy / 1e6, 3),
-           "mean_concurrency": round(total / busy, 3) if busy else 0.0, "peak_concurrency": peak}
+    return {"dispatches": n, "queues": len({e[2] for e in ev}), "overlapping_another_queue": int(sum(overl)),
+            "kernel_time_ms": round(total / 1e6, 3), "busy_time_ms": round(busy / 1e6, 3),
+            "mean_concurrency": round(total / busy, 3) if busy else 0.0, "peak_concurrency": peak}
+
+
+def overlap(dir_: str, out: str, cmd: str, gap_ms: float = 2.0) -> dict:
+    """Concurrency of kernel executions across hardware queues, from a
+    rocprofv3 kernel trace: how many dispatches overlap in time with a
+    dispatch of another queue, the summed kernel time over the time any
+    kernel runs (mean concurrency), and the most kernels running at once.
+    The trace is also cut into segments at idle gaps of gap_ms or more (one
+    segment per server run of a benchmark that runs several), each with the
+    same figures."""
+    path = _one(os.path.join(dir_, "**", "*kernel_trace.csv"))
+    rows = list(csv.DictReader(open(path)))
+    qcol = "Stream_Id" if rows and "Stream_Id" in rows[0] and any(r["Stream_Id"] not in ("", "0") for r in rows) \
+        else "Queue_Id"
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r[qcol], label(r["Kernel_Name"])) for r in rows)
+    res = _overlap_stats(ev)
+    segs, cur, last_end = [], [], None
+    for e in ev:
+        if cur and e[0] - last_end >= gap_ms * 1e6:
+            segs.append(cur)
+            cur = []
+        cur.append(e)
+        last_end = e[1] if last_end is None or not cur[:-1] else max(last_end, e[1])
+    if cur:
+        segs.append(cur)
+    res["segments"] = [_overlap_stats(sg) for sg in segs]
+    row = ("| {dispatches} | {queues} | {overlapping_another_queue} | {kernel_time_ms} | {busy_time_ms} "
+           "| {mean_concurrency} | {peak_concurrency} |")
+    head = ("| dispatches | queues | overlapping a dispatch of another queue | kernel time (ms) "
+            "| time any kernel runs (ms) | mean concurrency | peak concurrency |")
     lines = ["# Kernel overlap across queues (rocprofv3 kernel trace)", "", "Command:", "", "```", cmd, "```", "",
-             f"Queues seen ({qcol}): {len(queues)}.", "",
-             "| dispatches | overlapping a dispatch of another queue | kernel time (ms) | time any kernel runs (ms) "
-             "| mean concurrency | peak concurrency |", "|---:|---:|---:|---:|---:|---:|",
-             f"| {n} | {res['overlapping_another_queue']} | {res['kernel_time_ms']} | {res['busy_time_ms']} "
-             f"| {res['mean_concurrency']} | {peak} |", ""]
+             f"Queues identified by {qcol}.", "", "Whole trace:", "", head, "|---:|---:|---:|---:|---:|---:|---:|",
+             row.format(**res), "",
+             f"Segments (the trace cut at idle gaps of {gap_ms:g} ms or more):", "", "| segment " + head,
+             "|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    lines += [f"| {i} " + row.format(**sg) for i, sg in enumerate(res["segments"])]
     with open(out, "w") as f:
-        f.write("\n".join(lines) + "\n")
+        f.write("\n".join(lines + [""]))
     return res
 
 
@@ -279,6 +300,7 @@ def main() -> None:
     o.add_argument("--dir", required=True)
     o.add_argument("--out", required=True)
     o.add_argument("--cmd", required=True)
+    o.add_argument("--gap-ms", type=float, default=2.0)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -292,7 +314,7 @@ def main() -> None:
     if a.what == "stats":
         stats(a.dir, a.out, a.cmd)
     elif a.what == "overlap":
-        print(json.dumps(overlap(a.dir, a.out, a.cmd)))
+        print(json.dumps(overlap(a.dir, a.out, a.cmd, a.gap_ms)))
     else:
         traffic(a.fetch, a.write, a.copy_bytes, a.out, a.md, a.cmd_fetch, a.cmd_write,
                 a.only.split(",") if a.only else None)

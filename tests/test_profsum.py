@@ -83,3 +83,20 @@ def test_overlap_counts_concurrent_dispatches_of_other_queues(tmp_path):
     assert r["peak_concurrency"] == 2
     assert abs(r["mean_concurrency"] - 445 / 360) < 1e-3
     assert profsum.label(rows[0][3]) == "batch_warp_u8 c3 4x16x1x2"
+
+
+def test_overlap_segments_split_at_idle_gaps(tmp_path):
+    import csv
+    rows = [("0", 100, 200, "kr::k_copy(x)"), ("1", 150, 260, "kr::k_copy(x)"), ("0", 300, 400, "kr::k_copy(x)"),
+            ("0", 500, 600, "kr::k_copy(x)"), ("2", 550, 580, "kr::k_copy(x)"), ("2", 590, 595, "kr::k_copy(x)")]
+    with open(tmp_path / "r_kernel_trace.csv", "w") as f:
+        w = csv.writer(f)
+        w.writerow(["Queue_Id", "Start_Timestamp", "End_Timestamp", "Kernel_Name"])
+        w.writerows(rows)
+    # 100 ns: the 100 ns gap before the fourth dispatch splits, the 40 ns gap does not
+    r = profsum.overlap(str(tmp_path), str(tmp_path / "o.md"), "cmd", gap_ms=1e-4)
+    a, b = r["segments"]
+    assert (a["dispatches"], a["queues"], a["overlapping_another_queue"]) == (3, 2, 2)
+    assert (b["dispatches"], b["queues"], b["overlapping_another_queue"]) == (3, 2, 3)
+    assert "| 1 | 3 | 2 | 3 |" in (tmp_path / "o.md").read_text()
+    assert len(profsum.overlap(str(tmp_path), str(tmp_path / "o.md"), "cmd")["segments"]) == 1
