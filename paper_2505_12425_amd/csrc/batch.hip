@@ -32,9 +32,9 @@ __global__ __launch_bounds__(KT_THREADS) void k_batch(const TiledJob *__restrict
 {
     extern __shared__ uint32_t lds[];
     TileSeq seq(blockIdx.x, gridDim.x, bins.start);
-    // f32 outputs of a persistent grid leave through non-temporal stores, as
-    // in the per-image kernel; one-tile workgroups store plainly
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, PIPE>, MAXIT, PIPE>(G, e, lds, [&](TiledJob &t, int &tile) {
+    // f32 outputs leave through non-temporal stores (no kernel of the launch
+    // reads them back)
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, PIPE>(G, e, lds, [&](TiledJob &t, int &tile) {
         int g;
         if (!seq.take(g))
             return false;

@@ -23,10 +23,9 @@ __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, 
 {
     extern __shared__ uint32_t lds[];
     TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
-    // f32 outputs of a persistent grid leave through non-temporal stores (no
-    // kernel of the call reads them back); with one workgroup per tile plain
-    // stores measure faster on MI355X (4K warp to f32: 31.9 -> 30.0 us)
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, PERS>, MAXIT, PERS>(G, e, lds, [&](TiledJob &t, int &tile) {
+    // f32 outputs leave through non-temporal stores (no kernel of the call
+    // reads them back)
+    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, PERS>(G, e, lds, [&](TiledJob &t, int &tile) {
         if (!seq.take(tile))
             return false;
         t = job;
