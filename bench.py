@@ -11,6 +11,9 @@ uniform noise and a gradient, is
 all on torch's current stream through the C ABI.  Inputs are resident in HBM
 before timing starts; the source rotates over several copies (more bytes than
 the 256 MB Infinity Cache holds) so that every step reads its source from HBM.
+Outside the step, a "general_resize" record times the LDS-tiled resize that
+serves every ratio other than an exact 2 (4K -> 2560x1440, u8 and f32) the
+same way.
 The default line also carries a "systems" record (bounded versions of the
 workloads below): both batches as graph-replayed plans against per-image
 launches (eager from Python, and the same launches captured in one HIP
@@ -22,7 +25,8 @@ normalised, one launch over a work-list of tiles, vs per-image launches),
 --workload warpbatch (64 x 1080p warps, one launch, graph replay, vs
 per-image launches), --workload serve (continuous-batching request stream;
 p50/p99 latency), --workload ops (nearest-neighbour resize 4K <-> 1080p,
-flip, RGB -> gray and perspective warp at 4K), --workload warpseeds (the 4K
+flip, RGB -> gray, perspective warp, a quarter turn and the fused
+resample + gray forms at 4K), --workload warpseeds (the 4K
 warp for seeds 0-4 of its map).
 
 Prints ONE JSON line.  Kernel durations come from HIP events recorded around
@@ -48,6 +52,10 @@ from paper_2505_12425_amd.profsum import kernel_source_sha  # noqa: E402
 HBM_PEAK_GBPS = 8000.0
 TUNE_FILE = os.path.join(ROOT, "paper_2505_12425_amd", "tuned_mi355x.txt")
 SCRUB_BYTES = 512 << 20  # > the 256 MB last-level cache: evicts a source between tuner launches
+# Each kernel's destinations rotate over copies holding at least this many
+# bytes (twice the 256 MB last-level cache), so that a launch's output is
+# written back to HBM rather than rewritten in the cache by the next launch.
+OUT_ROTATE_BYTES = 512 << 20
 LINE = 128
 
 
@@ -250,9 +258,17 @@ def bench_4k(args, torch, kr, wl):
         "warp_f32": torch.empty((h, w, 3), dtype=torch.float32, device="cuda"),
     }
     names = list(outs)
+    # the LDS-tiled resize at a ratio other than 2 (every other resize runs
+    # it): 4K -> 2560x1440, timed like the step's kernels, outside the step
+    extra = {
+        "resize1440_u8": torch.empty((1440, 2560, 3), dtype=torch.uint8, device="cuda"),
+        "resize1440_f32": torch.empty((1440, 2560, 3), dtype=torch.float32, device="cuda"),
+    }
+    outs.update(extra)
+    rot = {n: Rotating(torch, t) for n, t in outs.items()}
 
     def launch(name, src):
-        d = outs[name]
+        d = rot[name].next()
         if name.startswith("resize"):
             kr.resize(src, d, border=kr.REPLICATE)
         else:
@@ -261,19 +277,23 @@ def bench_4k(args, torch, kr, wl):
     # algorithmic bytes per launch
     rs = resize_touched_bytes(h, w, 1080, 1920)
     ws = warp_touched_bytes(h, w, h, w, inv)
+    rs1440 = resize_touched_bytes(h, w, 1440, 2560)
     alg = {
         "resize_u8": rs + 1080 * 1920 * 3, "resize_f32": rs + 1080 * 1920 * 12,
         "warp_u8": ws + h * w * 3, "warp_f32": ws + h * w * 12,
+        "resize1440_u8": rs1440 + 1440 * 2560 * 3, "resize1440_f32": rs1440 + 1440 * 2560 * 12,
     }
-    px = {"resize_u8": 1080 * 1920, "resize_f32": 1080 * 1920, "warp_u8": h * w, "warp_f32": h * w}
-    px_per_step = sum(px.values())
+    px = {"resize_u8": 1080 * 1920, "resize_f32": 1080 * 1920, "warp_u8": h * w, "warp_f32": h * w,
+          "resize1440_u8": 1440 * 2560, "resize1440_f32": 1440 * 2560}
+    px_per_step = sum(px[n] for n in names)
+    profile_key = {"resize1440_u8": "resize_tiled_u8", "resize1440_f32": "resize_tiled_f32"}
 
     tuned = {}
     if args.tune_mode == "live":
         # timed with the caches scrubbed before each launch: the loops below
         # stream every source from HBM too
         scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device="cuda")
-        for n in names:
+        for n in outs:
             d = outs[n]
             if n.startswith("resize"):
                 tuned[n] = kr.autotune_image("resize", srcs[0], d, border=kr.REPLICATE, reps=15, scrub=scrub)
@@ -304,7 +324,10 @@ def bench_4k(args, torch, kr, wl):
     # stream (rotating cold sources) between one event pair, / launch count
     kern = {}
     reps = max(args.steps, 20)
-    for n in names:
+    for n in outs:
+        for _ in range(2):
+            launch(n, srcs[k % copies])
+            k += 1
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
@@ -317,19 +340,21 @@ def bench_4k(args, torch, kr, wl):
         gbps = alg[n] / (ms * 1e-3) / 1e9
         kern[n] = {"avg_us": round(ms * 1e3, 3), "launches": reps, "alg_bytes": alg[n], "GBps": round(gbps, 1),
                    "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(px[n] / (ms * 1e-3) / 1e9, 2),
-                   "traffic": _traffic_from_profiles(n)}
-    # the traffic-mix ceiling of each kernel: kr_hbm_stream reading one source
-    # copy (the same rotation) and writing that kernel's output buffer, i.e.
-    # the kernel's bytes each way with none of its arithmetic
+                   "traffic": _traffic_from_profiles(profile_key.get(n, n))}
+    # the traffic-mix ceiling of each kernel of the step: kr_hbm_stream
+    # reading one source copy (the same rotation) and writing that kernel's
+    # output buffer, i.e. the kernel's bytes each way with none of its
+    # arithmetic (the probe takes power-of-two size ratios only, which the
+    # 1440p outputs are not)
     for n in names:
         for i in range(3):
-            kr.hbm_stream(outs[n], srcs[(k + i) % copies])
+            kr.hbm_stream(rot[n].next(), srcs[(k + i) % copies])
         k += 3
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
         for _ in range(reps):
-            kr.hbm_stream(outs[n], srcs[k % copies])
+            kr.hbm_stream(rot[n].next(), srcs[k % copies])
             k += 1
         b.record()
         torch.cuda.synchronize()
@@ -345,8 +370,10 @@ def bench_4k(args, torch, kr, wl):
         "wall_s": wall,
         "config": {"workload": "4k: 3840x2160x3 u8 -> resize 1920x1080 + warp_affine 3840x2160 "
                                "(seed-0 rotation/scale/translation, constant-0 border), u8 and f32 outputs",
-                   "src": "3840x2160x3 u8", "cold_copies": copies, "px_per_step": px_per_step},
-        "dominant": dom, "kernels": kern, "cpu_args": (img, m), "autotune": tuned,
+                   "src": "3840x2160x3 u8", "cold_copies": copies,
+                   "out_rotation_MB": OUT_ROTATE_BYTES >> 20, "px_per_step": px_per_step},
+        "dominant": dom, "kernels": {n: kern[n] for n in names},
+        "general_resize": {n: kern[n] for n in extra}, "cpu_args": (img, m), "autotune": tuned,
     }
 
 
@@ -369,6 +396,21 @@ def _graph_of(torch, fn):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     return g
+
+
+class Rotating:
+    """Copies of one destination tensor, handed out in turn (at least
+    OUT_ROTATE_BYTES of them, at most 128)."""
+
+    def __init__(self, torch, t):
+        n = min(128, max(2, -(-OUT_ROTATE_BYTES // (t.numel() * t.element_size()))))
+        self.copies = [t] + [torch.empty_like(t) for _ in range(n - 1)]
+        self.i = 0
+
+    def next(self):
+        t = self.copies[self.i]
+        self.i = (self.i + 1) % len(self.copies)
+        return t
 
 
 def _time_loop(torch, fn, reps):
@@ -522,8 +564,8 @@ def bench_warpseeds(args, torch, kr, wl):
     img = wl.mixed_u8(h, w, 3, seed=0)
     copies = args.cold_copies
     srcs = [torch.from_numpy(img).cuda() for _ in range(copies)]
-    outs = {"warp_u8": torch.empty((h, w, 3), dtype=torch.uint8, device="cuda"),
-            "warp_f32": torch.empty((h, w, 3), dtype=torch.float32, device="cuda")}
+    outs = {"warp_u8": Rotating(torch, torch.empty((h, w, 3), dtype=torch.uint8, device="cuda")),
+            "warp_f32": Rotating(torch, torch.empty((h, w, 3), dtype=torch.float32, device="cuda"))}
     reps = max(args.steps, 20)
     seeds, total_px, total_ms, k = {}, 0, 0.0, 0
     for sd in range(5):
@@ -532,13 +574,13 @@ def bench_warpseeds(args, torch, kr, wl):
         row = {}
         for n, d in outs.items():
             for _ in range(args.warmup):
-                kr.warp_affine(srcs[k % copies], d, m, border=kr.CONSTANT, border_value=0.0)
+                kr.warp_affine(srcs[k % copies], d.next(), m, border=kr.CONSTANT, border_value=0.0)
                 k += 1
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             a.record()
             for _ in range(reps):
-                kr.warp_affine(srcs[k % copies], d, m, border=kr.CONSTANT, border_value=0.0)
+                kr.warp_affine(srcs[k % copies], d.next(), m, border=kr.CONSTANT, border_value=0.0)
                 k += 1
             b.record()
             torch.cuda.synchronize()
@@ -576,46 +618,46 @@ def bench_ops(args, torch, kr, wl):
 
     def nearest(dst_hw, dt):
         def make(src):
-            out = torch.empty(dst_hw + (3,), dtype=dt, device="cuda")
-            return lambda s: kr.resize_nearest(s, out)
+            out = Rotating(torch, torch.empty(dst_hw + (3,), dtype=dt, device="cuda"))
+            return lambda s: kr.resize_nearest(s, out.next())
         return make
 
     def flip(dt):
         def make(src):
-            out = torch.empty_like(src)
-            return lambda s: kr.flip(s, out, True, False)
+            out = Rotating(torch, torch.empty_like(src))
+            return lambda s: kr.flip(s, out.next(), True, False)
         return make
 
     hm = wl.random_homography(2160, 3840, np.random.default_rng(0), 0.12)
 
     def persp(dt):
         def make(src):
-            out = torch.empty(src.shape, dtype=dt, device="cuda")
-            return lambda s: kr.warp_perspective(s, out, hm, border=kr.CONSTANT)
+            out = Rotating(torch, torch.empty(src.shape, dtype=dt, device="cuda"))
+            return lambda s: kr.warp_perspective(s, out.next(), hm, border=kr.CONSTANT)
         return make
 
     def gray(dt):
         def make(src):
-            out = torch.empty(src.shape[:2] + (1,), dtype=dt, device="cuda")
-            return lambda s: kr.rgb_to_gray(s, out)
+            out = Rotating(torch, torch.empty(src.shape[:2] + (1,), dtype=dt, device="cuda"))
+            return lambda s: kr.rgb_to_gray(s, out.next())
         return make
 
     # a quarter turn: the permutation path of kr_warp_affine (no interpolation)
     rot90 = np.array([[0.0, 1.0, 0.0], [-1.0, 0.0, big[1] - 1.0]])
 
     def turn(src):
-        out = torch.empty((big[1], big[0], 3), dtype=torch.uint8, device="cuda")
-        return lambda s: kr.warp_affine(s, out, rot90)
+        out = Rotating(torch, torch.empty((big[1], big[0], 3), dtype=torch.uint8, device="cuda"))
+        return lambda s: kr.warp_affine(s, out.next(), rot90)
 
     m4k = wl.random_affine_4k(big[0], big[1], 0)
 
     def fused(op, dt):
         def make(src):
             hw = small if op == "resize" else big
-            out = torch.empty(hw + (1,), dtype=dt, device="cuda")
+            out = Rotating(torch, torch.empty(hw + (1,), dtype=dt, device="cuda"))
             if op == "resize":
-                return lambda s: kr.resize_gray(s, out)
-            return lambda s: kr.warp_affine_gray(s, out, m4k)
+                return lambda s: kr.resize_gray(s, out.next())
+            return lambda s: kr.warp_affine_gray(s, out.next(), m4k)
         return make
 
     u8, f32 = torch.uint8, torch.float32
@@ -872,6 +914,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8 fixed-point / f32", "data": "synthetic",
         "config": r["config"], "roofline": roof, "kernels": r["kernels"],
+        "general_resize": r["general_resize"],
         "tuning": dict(tuning, reports=r["autotune"]),
     }
     if not args.no_systems:

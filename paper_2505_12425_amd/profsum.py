@@ -86,7 +86,7 @@ def _point_key(kind: str, args: str) -> str | None:
 
 
 def bench_key(name: str) -> str | None:
-    """The benchmark's name for a kernel ('warp_f32', 'batch_resize_f32', ...).
+    """The benchmark's name for a kernel ('warp_f32', 'resize_tiled_u8', 'batch_resize_f32', ...).
     Nearest-resize kernels give a pattern with '{}' for the direction."""
     m = _TPL.search(name)
     if not m:
@@ -97,7 +97,10 @@ def bench_key(name: str) -> str | None:
     kind, op, c, f32 = m.groups()[:4]
     if c != "3":
         return None
-    return ("batch_" if kind == "batch" else "") + _OPS[op] + ("_f32" if f32 == "true" else "_u8")
+    # per-image resizes: 'resize_u8' names the exact-2x kernel of the 4K
+    # step, 'resize_tiled_u8' the LDS-tiled kernel of every other ratio
+    name = _OPS[op] + ("_tiled" if op == "0" and kind != "batch" else "")
+    return ("batch_" if kind == "batch" else "") + name + ("_f32" if f32 == "true" else "_u8")
 
 
 def _overlap_stats(ev) -> dict:

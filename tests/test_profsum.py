@@ -30,6 +30,9 @@ def test_labels_and_keys():
     assert profsum.bench_key(GRAY) == "gray_u8"
     assert profsum.bench_key(NEAR) == "nearest_{}_f32"
     assert profsum.bench_key(HALF) == "resize_f32" and profsum.label(HALF) == "resize_f32 c3 half"
+    tiled_r = "void kr::k_tiled<0, 3, false, 4, 16, 1, 1, 3, false>(kr::TiledJob, kr::Epilogue, kr::TileGeom)"
+    assert profsum.bench_key(tiled_r) == "resize_tiled_u8" and profsum.label(tiled_r) == "resize_u8 c3 4x16x1x1"
+    assert profsum.bench_key("void kr::k_batch<0, 3, true, 1, 64, 1, 4, 3, false>(x)") == "batch_resize_f32"
     assert profsum.bench_key(TILED_W.replace("<1, 3,", "<1, 4,")) is None  # only 3-channel kernels are benchmarked
 
 
