@@ -66,7 +66,7 @@ template <int C, bool DST_F32>
 __global__ __launch_bounds__(HS_TX * HS_TY) void k_half(ImageJob j, Epilogue e)
 {
     // f32 output: a wave's 256 pixels (3 or 4 KB) go through LDS so that each
-    // store instruction writes 64 consecutive 16-byte chunks
+    // (non-temporal) store instruction writes 64 consecutive 16-byte chunks
     __shared__ f32x4 xpose[DST_F32 ? HS_TY * HS_TX * C : 1];
     const int x = (blockIdx.x * HS_TX + threadIdx.x) * 4;
     const int xw = blockIdx.x * HS_TX * 4;  // the wave's first output column
@@ -126,13 +126,13 @@ __global__ __launch_bounds__(HS_TX * HS_TY) void k_half(ImageJob j, Epilogue e)
                 f32x4 *out = reinterpret_cast<f32x4 *>(row + (size_t)xw * C);
 #pragma unroll
                 for (int i = 0; i < C; i++)
-                    out[i * HS_TX + threadIdx.x] = buf[i * HS_TX + threadIdx.x];
+                    __builtin_nontemporal_store(buf[i * HS_TX + threadIdx.x], &out[i * HS_TX + threadIdx.x]);
                 // the next row's writes must not overtake these reads
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             } else {
-                store_f32_4<C>(row + (size_t)x * C, n, aligned, o);
+                store_f32_4<C, true>(row + (size_t)x * C, n, aligned, o);
             }
         }
     }

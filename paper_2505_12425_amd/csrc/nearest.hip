@@ -75,15 +75,11 @@ __global__ __launch_bounds__(NN_TX * NN_TY) void k_nearest(NearestJob j, Epilogu
                 for (int c = 0; c < C; c++)
                     o[c] = __builtin_fmaf(src[c], e.alpha[c], e.beta[c]);
             }
+            // non-temporal: no kernel of the call reads the output back
             float *d = static_cast<float *>(j.dst) + out;
-            if constexpr (C == 3) {
-                struct __attribute__((packed, aligned(4))) F3 { float a, b, c; };
-                *reinterpret_cast<F3 *>(d) = F3{o[0], o[1], o[2]};
-            } else {
 #pragma unroll
-                for (int c = 0; c < C; c++)
-                    d[c] = o[c];
-            }
+            for (int c = 0; c < C; c++)
+                __builtin_nontemporal_store(o[c], d + c);
         }
     }
 }

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(PM_THREADS) void k_permute(PermJob pj, Epilogue ep)
 #pragma unroll
                 for (int c = 0; c < C; c++)
                     o[k][c] = __builtin_fmaf((float)((P[k] >> (8 * c)) & 0xFFu), ep.alpha[c], ep.beta[c]);
-            store_f32_4<C>(static_cast<float *>(j.dst) + ((size_t)yy * j.dw + x) * C, n, aligned, o);
+            store_f32_4<C, true>(static_cast<float *>(j.dst) + ((size_t)yy * j.dw + x) * C, n, aligned, o);
         }
     }
 }

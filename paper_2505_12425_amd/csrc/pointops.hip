@@ -6,7 +6,8 @@
 // Launch shape as for the nearest-neighbour resize: 64 x 4 threads; u8
 // outputs take 4 consecutive pixels per thread (one 12- or 4-byte store),
 // f32 flips one pixel per thread (each store instruction of a wave is one
-// contiguous run), f32 gray 4 pixels (16 bytes).
+// contiguous run), f32 gray 4 pixels (16 bytes).  Outputs leave through
+// non-temporal stores: no kernel of the call reads them back.
 #include "kr_internal.h"
 #include "tiled.h"
 
@@ -114,11 +115,14 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_flip_f32(PtJob j, int fx, int
         uint32_t *d = dst + ((size_t)y * w + x) * C;
         if constexpr (C == 3) {
             struct __attribute__((packed, aligned(4))) W3 { uint32_t a, b, c; };
-            *reinterpret_cast<W3 *>(d) = *reinterpret_cast<const W3 *>(s);
+            const W3 v = *reinterpret_cast<const W3 *>(s);
+            __builtin_nontemporal_store(v.a, d);
+            __builtin_nontemporal_store(v.b, d + 1);
+            __builtin_nontemporal_store(v.c, d + 2);
         } else {
 #pragma unroll
             for (int c = 0; c < C; c++)
-                d[c] = s[c];
+                __builtin_nontemporal_store(s[c], d + c);
         }
     }
 }
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_gray(PtJob j, Epilogue e)
         if constexpr (DST_F32) {
             float *d = static_cast<float *>(dst) + lin;
             if (n == 4 && (w & 3) == 0) {
-                *reinterpret_cast<f32x4 *>(d) = f32x4{o[0], o[1], o[2], o[3]};
+                __builtin_nontemporal_store(f32x4{o[0], o[1], o[2], o[3]}, reinterpret_cast<f32x4 *>(d));
             } else {
                 for (int k = 0; k < n; k++)
                     d[k] = o[k];
@@ -198,7 +202,8 @@ __global__ __launch_bounds__(PO_TX * PO_TY) void k_gray(PtJob j, Epilogue e)
         } else {
             uint8_t *d = static_cast<uint8_t *>(dst) + lin;
             if (n == 4 && (w & 3) == 0) {
-                *reinterpret_cast<uint32_t *>(d) = g[0] | (g[1] << 8) | (g[2] << 16) | (g[3] << 24);
+                __builtin_nontemporal_store(g[0] | (g[1] << 8) | (g[2] << 16) | (g[3] << 24),
+                                            reinterpret_cast<uint32_t *>(d));
             } else {
                 for (int k = 0; k < n; k++)
                     d[k] = (uint8_t)g[k];
