@@ -3,6 +3,9 @@
     python -m paper_2505_12425_amd.profsum stats --dir D --out F.md --cmd "..."
         kernel-trace statistics (``rocprofv3 --kernel-trace --stats -f csv``)
         of every kernel, with readable labels.
+    python -m paper_2505_12425_amd.profsum counters --dir D --out F.md --cmd "..." --px warp_u8=8294400,...
+        shader-sequencer counters of one --pmc pass per benchmark kernel
+        (instructions per output pixel, or the split of wave time).
     python -m paper_2505_12425_amd.profsum traffic --fetch D1 --write D2 \\
             --copy-bytes N --out F.json --md F.md --cmd-fetch "..." --cmd-write "..." \\
             [--only warp_f32,warp_u8]
@@ -292,6 +295,62 @@ def traffic(fetch_dir, write_dir, copy_bytes, out, md, cmd_fetch, cmd_write, onl
             f.write("\n".join(lines) + "\n")
 
 
+def _all_counter_means(dir_: str):
+    """Mean value per dispatch of every counter, per (kernel, grid size)."""
+    path = _one(os.path.join(dir_, "**", "*counter_collection.csv"))
+    acc = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        acc[(r["Kernel_Name"], int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: ({c: sum(v) / len(v) for c, v in cs.items()}, max(len(v) for v in cs.values()))
+            for k, cs in acc.items()}
+
+
+def counters(dir_: str, out: str, cmd: str, px: dict) -> dict:
+    """Shader-sequencer counters of the benchmark's kernels, one --pmc pass:
+    instructions per output pixel (SQ_INSTS_*: wave instructions, x 64 /
+    output pixels) and LDS bank-conflict cycles per LDS instruction, or the
+    split of wave time (SQ_WAVE_CYCLES) into waiting, issue-blocked and
+    active.  px maps a benchmark key to the kernel's output pixels."""
+    means = _all_counter_means(dir_)
+    keyed = _keyed({k: (0.0, n) for k, (_, n) in means.items()})
+    rows = {}
+    for key, ents in sorted(keyed.items()):
+        if key not in px:
+            continue
+        cs, n = means[ents[0]]
+        rows[key] = {"kernel": label(ents[0][0]), "dispatches": n, **{c: round(v, 1) for c, v in cs.items()}}
+    lines = ["# Shader-sequencer counters of the benchmark kernels (rocprofv3 --pmc)", "", "Command:", "", "```",
+             cmd, "```", ""]
+    if any("SQ_INSTS_VALU" in r for r in rows.values()):
+        lines += ["Per dispatch, averaged over the run's dispatches of each kernel.  Instruction counts are wave",
+                  "instructions, so `x 64 / output pixels` gives instructions per output pixel.",
+                  "SQ_LDS_BANK_CONFLICT counts cycles the LDS stalls on bank conflicts.", "",
+                  "| kernel | dispatches | waves | VALU / px | SALU / px | LDS instr / px | conflict cycles / LDS instr |",
+                  "|---|---:|---:|---:|---:|---:|---:|"]
+        for key, r in rows.items():
+            f = 64.0 / px[key]
+            lds = r.get("SQ_INSTS_LDS", 0.0)
+            conf = f"{r.get('SQ_LDS_BANK_CONFLICT', 0.0) / lds:.2f}" if lds else "-"
+            lines.append(f"| {key} ({r['kernel']}) | {r['dispatches']} | {r.get('SQ_WAVES', 0):.0f} | "
+                         f"{r.get('SQ_INSTS_VALU', 0) * f:.1f} | {r.get('SQ_INSTS_SALU', 0) * f:.1f} | "
+                         f"{lds * f:.2f} | {conf} |")
+    if any("SQ_WAVE_CYCLES" in r for r in rows.values()):
+        lines += ["Fractions of SQ_WAVE_CYCLES (summed over waves), averaged over each kernel's dispatches.",
+                  "wait = waiting on a dependency (s_waitcnt, barrier); issue = ready but waiting for an",
+                  "instruction slot; active = issuing, of which VALU, LDS and VMEM are shown.", "",
+                  "| kernel | wait | issue | active | VALU | LDS | VMEM |", "|---|---:|---:|---:|---:|---:|---:|"]
+        for key, r in rows.items():
+            wc = r.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+            lines.append(f"| {key} ({r['kernel']}) | {r.get('SQ_WAIT_ANY', 0) / wc:.2f} | "
+                         f"{r.get('SQ_WAIT_INST_ANY', 0) / wc:.2f} | {r.get('SQ_ACTIVE_INST_ANY', 0) / wc:.2f} | "
+                         f"{r.get('SQ_ACTIVE_INST_VALU', 0) / wc:.2f} | {r.get('SQ_ACTIVE_INST_LDS', 0) / wc:.2f} | "
+                         f"{r.get('SQ_ACTIVE_INST_VMEM', 0) / wc:.2f} |")
+    lines += ["", f"Kernel sources hash: {kernel_source_sha()}"]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -304,6 +363,11 @@ def main() -> None:
     o.add_argument("--out", required=True)
     o.add_argument("--cmd", required=True)
     o.add_argument("--gap-ms", type=float, default=2.0)
+    q = sub.add_parser("counters")
+    q.add_argument("--dir", required=True)
+    q.add_argument("--out", required=True)
+    q.add_argument("--cmd", required=True)
+    q.add_argument("--px", required=True, help="key=pixels,... output pixels of each benchmark kernel")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -316,6 +380,8 @@ def main() -> None:
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.dir, a.out, a.cmd)
+    elif a.what == "counters":
+        counters(a.dir, a.out, a.cmd, {k: int(v) for k, v in (e.split("=") for e in a.px.split(","))})
     elif a.what == "overlap":
         print(json.dumps(overlap(a.dir, a.out, a.cmd, a.gap_ms)))
     else:

@@ -103,3 +103,29 @@ def test_overlap_segments_split_at_idle_gaps(tmp_path):
     assert (b["dispatches"], b["queues"], b["overlapping_another_queue"]) == (3, 2, 3)
     assert "| 1 | 3 | 2 | 3 |" in (tmp_path / "o.md").read_text()
     assert len(profsum.overlap(str(tmp_path), str(tmp_path / "o.md"), "cmd")["segments"]) == 1
+
+
+def test_counters_per_pixel_and_wave_states(tmp_path):
+    rows = []
+    for c, v in (("SQ_INSTS_VALU", 1000.0), ("SQ_INSTS_SALU", 500.0), ("SQ_INSTS_LDS", 40.0),
+                 ("SQ_LDS_BANK_CONFLICT", 80.0), ("SQ_WAVES", 16.0)):
+        rows += [(TILED_W, 4096, c, v), (TILED_W, 4096, c, v * 3)]  # two dispatches: mean = 2 v
+    path = tmp_path / "c"
+    os.makedirs(path)
+    with open(path / "r_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writerows(rows)
+    r = profsum.counters(str(path), str(tmp_path / "c.md"), "cmd", {"warp_f32": 64 * 10})
+    assert r["warp_f32"]["SQ_INSTS_VALU"] == 2000.0 and r["warp_f32"]["dispatches"] == 2
+    text = (tmp_path / "c.md").read_text()
+    assert "| 32 | 200.0 | 100.0 | 8.00 | 2.00 |" in text  # 2000 x 64 / 640 VALU per pixel
+    rows = [(TILED_W, 4096, "SQ_WAVE_CYCLES", 100.0), (TILED_W, 4096, "SQ_WAIT_ANY", 40.0),
+            (TILED_W, 4096, "SQ_WAIT_INST_ANY", 30.0), (TILED_W, 4096, "SQ_ACTIVE_INST_ANY", 30.0),
+            (TILED_W, 4096, "SQ_ACTIVE_INST_VALU", 20.0)]
+    with open(path / "r_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writerows(rows)
+    profsum.counters(str(path), str(tmp_path / "s.md"), "cmd", {"warp_f32": 640})
+    assert "| 0.40 | 0.30 | 0.30 | 0.20 | 0.00 | 0.00 |" in (tmp_path / "s.md").read_text()
