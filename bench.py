@@ -448,8 +448,9 @@ def bench_batch(args, torch, kr, wl):
         for s, d in zip(srcs, dsts):
             kr.resize(s, d, border=kr.REPLICATE, mean=mean, std=std)
 
-    def batched():
-        kr.resize_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws)
+    # the eager batch entry point on arguments marshalled once (building the
+    # ctypes item array from 256 tensors costs more in Python than the call)
+    batched = kr.prepare_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws)
 
     g_img = _graph_of(torch, per_image)
     for f in (per_image, batched, plan.launch, g_img.replay):

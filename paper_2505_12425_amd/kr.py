@@ -431,6 +431,29 @@ def resize_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean
                                    _stream(stream)))
 
 
+def prepare_batch(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None, workspace=None,
+                  stream=None, layout: int = LAYOUT_HWC):
+    """resize_batch with the arguments marshalled once: returns a function
+    that calls kr_resize_batch_ex on the same items each time (the library
+    validates and builds the work-list on every call, as resize_batch does)."""
+    import torch
+    arr, n, c, st, dt = _batch_items(specs, layout)
+    if n == 0:
+        return lambda: None
+    need = batch_workspace_size(n)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    norm = _normalize(mean, std, c)
+    args = (arr, n, c, st, dt, border, float(border_value), norm, int(layout), workspace.data_ptr(),
+            workspace.numel() * workspace.element_size(), _stream(stream))
+    fn = lib().kr_resize_batch_ex
+
+    def call():
+        check(fn(*args))
+    call.keep = (arr, norm, workspace)  # the marshalled arguments live as long as the function
+    return call
+
+
 def resize_batch_noalloc(specs, border: int = REPLICATE, border_value: float = 0.0, mean=None, std=None,
                          stream=None, layout: int = LAYOUT_HWC) -> None:
     """kr_resize_batch_noalloc: resize_batch with the work-list in the

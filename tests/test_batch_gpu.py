@@ -131,6 +131,33 @@ def test_batch_single_item_and_empty():
     kr.resize_batch([])  # nothing to do
 
 
+def test_prepared_batch_calls_equal_resize_batch():
+    """kr.prepare_batch marshals once and calls kr_resize_batch_ex again on
+    every call: each call equals resize_batch, bit for bit."""
+    rng = np.random.default_rng(5)
+    specs, ref = [], []
+    for i in range(12):
+        h, w = int(rng.integers(20, 300)), int(rng.integers(20, 300))
+        src = torch.from_numpy(wl.uniform_u8(h, w, 3, seed=200 + i)).cuda()
+        op = "warp" if i % 3 == 0 else "resize"
+        dh, dw = (h, w) if op == "warp" else (int(rng.integers(8, 200)), int(rng.integers(8, 200)))
+        sp = {"op": op, "src": src, "dst": torch.empty((dh, dw, 3), dtype=torch.float32, device="cuda")}
+        if op == "warp":
+            sp["m"] = wl.random_affine_batch(h, w, rng)
+        specs.append(sp)
+        ref.append(dict(sp, dst=torch.empty_like(sp["dst"])))
+    kr.resize_batch(ref, border=kr.CONSTANT, border_value=7.0, mean=MEAN, std=STD)
+    call = kr.prepare_batch(specs, border=kr.CONSTANT, border_value=7.0, mean=MEAN, std=STD)
+    for rep in range(3):
+        for sp in specs:
+            sp["dst"].fill_(-1.0)
+        call()
+        torch.cuda.synchronize()
+        for a, b in zip(specs, ref):
+            assert torch.equal(a["dst"], b["dst"]), f"call {rep}"
+    kr.prepare_batch([])()  # nothing to do
+
+
 @pytest.mark.parametrize("out", ["u8", "f32"])
 def test_warp_batch_all_lds_classes(out):
     """Warps whose boxes fit the primary tile shape, only 32x32 tiles, or no
