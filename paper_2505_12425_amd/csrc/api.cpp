@@ -320,8 +320,8 @@ kr_status kr_resize_bilinear_gray(const void *src, int src_h, int src_w, size_t 
     std::memset(&j, 0, sizeof j);
     set_source(j, src, src_h, src_w, 3, KR_U8, src_pitch);
     j.dst = dst; j.dh = dst_h; j.dw = dst_w;
-    const hipError_t err = launch_tiled(OP_RESIZE, 3, dst_t, j, make_gray_epilogue(border, border_value, norm),
-                                        (hipStream_t)stream);
+    const hipError_t err = launch_resize_gray(dst_t, j, make_gray_epilogue(border, border_value, norm),
+                                              (hipStream_t)stream);
     if (err != hipSuccess)
         return fail(KR_ERR_HIP, "resize launch failed: %s", hipGetErrorString(err));
     return KR_OK;

@@ -17,6 +17,13 @@ hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, con
     return launch_generic(OP_RESIZE, c, st, dt, j, e, s);
 }
 
+hipError_t launch_resize_gray(kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
+{
+    if (is_half_scale(KR_U8, j))
+        return launch_half(3, dt, j, e, s);
+    return launch_tiled(OP_RESIZE, 3, dt, j, e, s);
+}
+
 hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
     // pixel permutations (flips, quarter turns, transposes with whole offsets)

@@ -17,7 +17,9 @@
 // results leave as 4-pixel stores (contiguous across the wave); f32 results
 // are transposed through LDS within the wave first, so that each store
 // instruction writes 64 consecutive 16-byte chunks instead of chunks 3 or 4
-// apart.
+// apart.  The fused gray form (an RGB source, the gray epilogue) stores the luma
+// of each mean pixel through the tiled engine's gray stores, so its bits
+// equal the tiled kernel's for the same resize.
 #include "kr_device.h"
 #include "tiled.h"
 
@@ -102,6 +104,12 @@ __global__ __launch_bounds__(HS_TX * HS_TY) void k_half(ImageJob j, Epilogue e)
                     p |= ((s[k][c] + 2u) >> 2) << (8 * c);
                 P[k] = p;
             }
+            if constexpr (C == 3) {
+                if (e.gray) {  // the fused gray form: luma of each mean pixel
+                    store_gray_u8<4>(j, y, x, j.dw, P);
+                    continue;
+                }
+            }
             store_u8_4<C>(static_cast<uint8_t *>(j.dst) + ((size_t)y * j.dw + x) * C, n, aligned, P);
         } else {
             float o[4][C];
@@ -110,6 +118,12 @@ __global__ __launch_bounds__(HS_TX * HS_TY) void k_half(ImageJob j, Epilogue e)
 #pragma unroll
                 for (int c = 0; c < C; c++)
                     o[k][c] = __builtin_fmaf((float)s[k][c] * 0.25f, e.alpha[c], e.beta[c]);
+            if constexpr (C == 3) {
+                if (e.gray) {  // channel values unnormalised (alpha 1, beta 0); the gray gets galpha, gbeta
+                    store_gray_f32<C, 4, true>(j, e, y, x, j.dw, o);
+                    continue;
+                }
+            }
             float *row = static_cast<float *>(j.dst) + (size_t)y * j.dw * C;
             if (aligned && xw + 4 * HS_TX <= j.dw) {
                 // whole wave inside the row (uniform per wave): lane l's 4 C

@@ -375,14 +375,15 @@ __device__ __forceinline__ void store_u8_px(uint8_t *row, int x, int x_end, bool
 {
     if constexpr (C == 4) {
         if (x < x_end)
-            *reinterpret_cast<uint32_t *>(row + 4 * (size_t)x) = P;
+            __builtin_nontemporal_store(P, reinterpret_cast<uint32_t *>(row + 4 * (size_t)x));
     } else {
         const uint32_t Pn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)P, 0xF9, 0xF, 0xF, false);
         const int j = lane_id() & 3;
         const int xq = x - j;
         if (row_aligned && xq + 3 < x_end) {
             if (j < 3)
-                *reinterpret_cast<uint32_t *>(row + 3 * (size_t)xq + 4 * j) = __builtin_amdgcn_perm(Pn, P, sel);
+                __builtin_nontemporal_store(__builtin_amdgcn_perm(Pn, P, sel),
+                                            reinterpret_cast<uint32_t *>(row + 3 * (size_t)xq + 4 * j));
         } else if (x < x_end) {
             uint8_t *q = row + 3 * (size_t)x;
             q[0] = (uint8_t)P;
@@ -463,8 +464,9 @@ __device__ __forceinline__ void store_gray_u8(const ImageJob &j, int y, int x, i
         return;
     if constexpr (PX == 4) {
         if (n == 4 && (j.dw & 3) == 0) {
-            *reinterpret_cast<uint32_t *>(row + x) =
-                luma_u8(P[0]) | (luma_u8(P[1]) << 8) | (luma_u8(P[2]) << 16) | (luma_u8(P[3]) << 24);
+            __builtin_nontemporal_store(
+                luma_u8(P[0]) | (luma_u8(P[1]) << 8) | (luma_u8(P[2]) << 16) | (luma_u8(P[3]) << 24),
+                reinterpret_cast<uint32_t *>(row + x));
             return;
         }
     }
@@ -525,7 +527,8 @@ __device__ __forceinline__ void store_row_u8(const ImageJob &j, const Epilogue &
             if (n == 4 && (j.dw & 3) == 0) {
                 const uint32_t lo = __builtin_amdgcn_perm(P[1], P[0], 0x0C0C0400u + 0x00000101u * c);
                 const uint32_t hi = __builtin_amdgcn_perm(P[3], P[2], 0x0C0C0400u + 0x00000101u * c);
-                *reinterpret_cast<uint32_t *>(row + c * plane) = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+                __builtin_nontemporal_store(__builtin_amdgcn_perm(hi, lo, 0x05040100u),
+                                            reinterpret_cast<uint32_t *>(row + c * plane));
                 continue;
             }
         }

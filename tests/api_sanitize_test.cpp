@@ -29,6 +29,7 @@ hipError_t launch_nearest(int, kr_dtype, kr_dtype, const ImageJob &j, const Epil
 hipError_t launch_flip(int, kr_dtype, const ImageJob &j, int, int, hipStream_t) { return record(j); }
 hipError_t launch_gray(kr_dtype, kr_dtype, const ImageJob &j, const Epilogue &, hipStream_t) { return record(j); }
 hipError_t launch_tiled(int, int, kr_dtype, const ImageJob &j, const Epilogue &, hipStream_t) { return record(j); }
+hipError_t launch_resize_gray(kr_dtype, const ImageJob &j, const Epilogue &, hipStream_t) { return record(j); }
 hipError_t launch_copy(void *, const void *, size_t, hipStream_t) { g_calls++; return hipSuccess; }
 hipError_t launch_stream(void *, size_t, const void *, int, int, hipStream_t) { g_calls++; return hipSuccess; }
 }  // namespace kr
