@@ -319,8 +319,9 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 
 // Tile shapes tried in order (the first whose LDS footprint fits is used).
 // KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent" override the
-// first choice.
-static int default_cfgs(int op, bool f32, TileCfg *out)
+// first choice.  gather: a resize whose taps are read from global memory
+// (it shrinks x by more than 3).
+static int default_cfgs(int op, bool f32, bool gather, TileCfg *out)
 {
     int n = 0;
     const char *tile = std::getenv("KR_TILE");
@@ -347,6 +348,12 @@ static int default_cfgs(int op, bool f32, TileCfg *out)
             add(4, 16, 1, 2, false);
         }
         add(1, 64, 1, 8, false);
+    } else if (gather) {
+        // nothing is staged: a thread's outputs are a chain of dependent tap
+        // loads, so short chains (4 pixels of one row per thread) and many
+        // small tiles win (the 256 mixed-size images of the batch workload,
+        // 201 of them past 3x, resized one by one: 2.92 -> 1.42 ms)
+        add(4, 64, 1, 1, false);
     } else {
         add(1, 64, 2, 4, false);
         add(4, 16, 1, 1, false);
@@ -362,7 +369,7 @@ static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
     TileCfg tuned;
     if (tune_lookup(tune_key_image(OP, C, F32, j), &tuned))
         cfgs[n++] = tuned;
-    n += default_cfgs(OP, F32, cfgs + n);
+    n += default_cfgs(OP, F32, wants_gather(j, OP), cfgs + n);
     for (int i = 0; i < n; i++) {
         bool fits = false;
         const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, false, fits);
