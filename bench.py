@@ -296,9 +296,9 @@ def bench_4k(args, torch, kr, wl):
         for n in outs:
             d = outs[n]
             if n.startswith("resize"):
-                tuned[n] = kr.autotune_image("resize", srcs[0], d, border=kr.REPLICATE, reps=15, scrub=scrub)
+                tuned[n] = kr.autotune_image("resize", srcs[0], d, border=kr.REPLICATE, reps=60, scrub=scrub)
             else:
-                tuned[n] = kr.autotune_image("warp", srcs[0], d, m, border=kr.CONSTANT, reps=15, scrub=scrub)
+                tuned[n] = kr.autotune_image("warp", srcs[0], d, m, border=kr.CONSTANT, reps=60, scrub=scrub)
         del scrub
     # Every launch reads a source copy that the previous (copies - 1) launches
     # did not touch, so no launch finds its source in the caches.
@@ -439,7 +439,7 @@ def bench_batch(args, torch, kr, wl):
     tuned = ""
     if args.tune_mode == "live":
         scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device="cuda")
-        tuned = kr.autotune_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws, reps=10,
+        tuned = kr.autotune_batch(specs, border=kr.REPLICATE, mean=mean, std=std, workspace=ws, reps=30,
                                   scrub=scrub)
         del scrub
     plan = kr.BatchPlan(specs, border=kr.REPLICATE, mean=mean, std=std)
@@ -512,7 +512,7 @@ def bench_warpbatch(args, torch, kr, wl):
     tuned = ""
     if args.tune_mode == "live":
         scrub = torch.empty(SCRUB_BYTES, dtype=torch.uint8, device="cuda")
-        tuned = kr.autotune_batch(specs, border=kr.CONSTANT, reps=10, scrub=scrub)
+        tuned = kr.autotune_batch(specs, border=kr.CONSTANT, reps=30, scrub=scrub)
         del scrub
     plan = kr.BatchPlan(specs, border=kr.CONSTANT)
 

@@ -29,7 +29,7 @@ struct TileCfg {
 #define KR_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 32, 1, 2) X(4, 64, 1, 1) X(4, 64, 1, 2) \
     X(1, 64, 2, 4) X(1, 64, 4, 2)
 #define KR_BATCH_WARP_CFGS(X) X(4, 16, 1, 1) X(4, 16, 1, 2) X(4, 8, 1, 1) X(1, 64, 1, 4) X(1, 64, 1, 8)
-#define KR_BATCH_RESIZE_CFGS(X) X(4, 16, 1, 1) X(1, 64, 1, 4) X(1, 64, 2, 4)
+#define KR_BATCH_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 64, 1, 1) X(1, 64, 1, 4) X(1, 64, 2, 4)
 
 // Launch one image with an explicit configuration; fits = false (nothing
 // launched) when its LDS footprint exceeds the per-workgroup budget.
