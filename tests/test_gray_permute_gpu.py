@@ -29,7 +29,7 @@ def _gray_out(h, w, out):
 
 
 RESIZES = [(480, 640, 240, 320), (2160, 3840, 1080, 1920), (2160, 3840, 1440, 2560), (97, 131, 301, 277),
-           (1, 1, 5, 7), (40, 3000, 41, 17), (333, 257, 333, 257)]
+           (1, 1, 5, 7), (40, 3000, 41, 17), (333, 257, 333, 257), (74, 106, 37, 53)]
 
 
 @pytest.mark.parametrize("shape", RESIZES, ids=[f"{a}x{b}-{c}x{d}" for a, b, c, d in RESIZES])
@@ -85,12 +85,12 @@ def test_fused_gray_equals_the_two_operators(out):
     dt = torch.uint8 if out == "u8" else torch.float32
     mean, std = (MEAN, STD) if out == "norm" else (None, None)
     m = wl.affine_compose(1000, 1400, 33.0, 1.15, 0.05, -20.0, 14.0)
-    for op in ("resize", "warp"):
-        dh, dw = (613, 777) if op == "resize" else (1000, 1400)
+    for op in ("resize", "resize2x", "warp"):
+        dh, dw = {"resize": (613, 777), "resize2x": (500, 700), "warp": (1000, 1400)}[op]
         rgb = torch.empty((dh, dw, 3), dtype=dt, device="cuda")
         two = _gray_out(dh, dw, "u8" if out == "u8" else "f32")
         one = _gray_out(dh, dw, "u8" if out == "u8" else "f32")
-        if op == "resize":
+        if op.startswith("resize"):  # resize2x: the exact-2x kernel on both sides
             kr.resize(s, rgb)
             kr.resize_gray(s, one, mean=mean, std=std)
         else:
@@ -108,11 +108,15 @@ def test_gray_views_equal_contiguous_copies():
     copy = view.contiguous()
     for fn, args in ((kr.resize_gray, ()), (kr.warp_affine_gray, (wl.affine_compose(264, 428, 12.0, 1.0, 0.0,
                                                                                       3.0, 1.0),))):
-        a, b = _gray_out(200, 300, "u8"), _gray_out(200, 300, "u8")
-        fn(view, a, *args)
-        fn(copy, b, *args)
-        torch.cuda.synchronize()
-        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        for dh, dw in ((200, 300), (132, 214)):  # (132, 214): an exact 2x resize of the view
+            if fn is kr.warp_affine_gray and dh != 200:
+                continue
+            for out in ("u8", "f32"):
+                a, b = _gray_out(dh, dw, out), _gray_out(dh, dw, out)
+                fn(view, a, *args)
+                fn(copy, b, *args)
+                torch.cuda.synchronize()
+                assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), (fn.__name__, dh, dw, out)
 
 
 def test_gray_validation():
