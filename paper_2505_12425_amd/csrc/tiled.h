@@ -861,6 +861,19 @@ __device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const
 
 // Write the prefetched groups to LDS, then stage any remaining work items
 // directly (boxes larger than MAXIT groups per thread), MAXIT at a time.
+// prefetch() by the whole workgroup at raised wave priority: while other
+// workgroups of the CU interpolate, the waves issuing a tile's staging loads
+// get the instruction slots first, so the loads leave early (4K warp to f32
+// 31.6 -> 30.6 us; u8 outputs unchanged).
+template <int OP, int C, int MAXIT>
+__device__ __forceinline__ void prefetch_urgent(const TiledJob &t, const Plan &p, const TileGeom &G,
+                                                Prefetch<C, MAXIT> &pf)
+{
+    __builtin_amdgcn_s_setprio(2);
+    prefetch<OP, C, MAXIT>(t, p, G, pf, threadIdx.x);
+    __builtin_amdgcn_s_setprio(0);
+}
+
 template <int OP, int C, int MAXIT, int NLT = KT_THREADS>
 __device__ __forceinline__ void commit(const TiledJob &t, const Plan &p, const TileGeom &G,
                                        Prefetch<C, MAXIT> &pf, uint32_t *lds, int lt)
@@ -1489,7 +1502,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
     if constexpr (!PIPE) {
         if (!p.direct) {
             Prefetch<C, MAXIT> pf;
-            prefetch<OP, C, MAXIT>(t, p, G, pf, threadIdx.x);
+            prefetch_urgent<OP, C, MAXIT>(t, p, G, pf);
             commit<OP, C, MAXIT>(t, p, G, pf, lds, threadIdx.x);
         }
         if constexpr (OP == OP_RESIZE)
@@ -1510,7 +1523,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         return;
     }
     Prefetch<C, MAXIT> pf;
-    prefetch<OP, C, MAXIT>(t, p, G, pf, threadIdx.x);
+    prefetch_urgent<OP, C, MAXIT>(t, p, G, pf);
     while (true) {
         if (!p.direct)
             commit<OP, C, MAXIT>(t, p, G, pf, lds, threadIdx.x);
@@ -1527,7 +1540,7 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         Plan np;
         if (more) {
             np = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
-            prefetch<OP, C, MAXIT>(nt, np, G, pf, threadIdx.x);
+            prefetch_urgent<OP, C, MAXIT>(nt, np, G, pf);
         }
         if (p.blank)
             fill_blank<C, F32, L>(t, p, e);
