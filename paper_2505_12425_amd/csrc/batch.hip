@@ -101,7 +101,15 @@ hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue 
     return f ? launch_group_c<OP_RESIZE, 4, true>(g, e, s) : launch_group_c<OP_RESIZE, 4, false>(g, e, s);
 }
 
-constexpr size_t KB_LDS_BUDGET = 48 * 1024;  // per workgroup, for the batch's widest box
+// LDS per workgroup of a batch launch.  Every workgroup of the launch takes
+// the same LDS size, the widest pitch times the most rows over its staged
+// items, and that size sets the resident workgroups per CU (160 KB / size).
+// The 64 warps of 1080p images: 0.37 ms per plan when only each item's own
+// box had to fit 48 KB (the launch box came to 49 KB, three workgroups per
+// CU); with the launch box held to the budget (fit_launch_box), 0.335 ms at
+// 48 KB, 0.330 ms at 32 KB (five per CU), 0.361 ms at 28 KB (more tiles on
+// the gather path).  The 256-image resize batch is the same at all of them.
+constexpr size_t KB_LDS_BUDGET = 32 * 1024;
 
 // Tile shape of a batch group when the batch class is not tuned: small
 // tiles, so that batches of small outputs still produce many tiles.
@@ -125,6 +133,43 @@ static double item_cost(const ImageJob &j, int op, bool f32, int c, bool staged)
                                          : std::fabs(j.inv[0] * j.inv[4] - j.inv[1] * j.inv[3]);
     const double bytes = px * c * ((f32 ? 4.0 : 1.0) + std::min(ratio, 4.0));
     return staged ? bytes : 1.5 * bytes;
+}
+
+// Keep the launch's box within the budget: while the widest pitch times the
+// most rows over the staged items exceeds it, the staged item with the
+// largest box among those that set the pitch or the rows moves to the gather
+// path.
+static void fit_launch_box(const std::vector<ImageJob> &imgs, int op, int tw, int th, size_t budget,
+                           std::vector<bool> &stage)
+{
+    const int n = (int)imgs.size();
+    std::vector<TileGeom> geo(n);
+    for (int i = 0; i < n; i++)
+        geo[i] = stage[i] ? tile_geom(imgs[i], op, tw, th) : TileGeom{0, 0};
+    while (true) {
+        TileGeom G{0, 0};
+        for (int i = 0; i < n; i++)
+            if (stage[i]) {
+                G.pitch = std::max(G.pitch, geo[i].pitch);
+                G.rows = std::max(G.rows, geo[i].rows);
+            }
+        if (tile_lds_bytes(G, tw, th) <= budget)
+            return;
+        int drop = -1;
+        long best = -1;
+        for (int i = 0; i < n; i++) {
+            if (!stage[i] || (geo[i].pitch != G.pitch && geo[i].rows != G.rows))
+                continue;
+            const long area = (long)geo[i].pitch * geo[i].rows;
+            if (area > best) {
+                best = area;
+                drop = i;
+            }
+        }
+        if (drop < 0)
+            return;
+        stage[drop] = false;
+    }
 }
 
 // One group: job table (tile prefix sums, items ordered bin by bin), per-XCD
@@ -203,7 +248,8 @@ static bool fits(const ImageJob &j, int op, const TileCfg &c, size_t budget)
 // would set the LDS size of every workgroup of the launch: such items read
 // their taps directly, which keeps the group's LDS and so its occupancy at the
 // size the milder items need.  Warps whose boxes exceed the batch LDS budget
-// (strong shrinks) likewise take the global-gather path for their tiles.
+// (strong shrinks) likewise take the global-gather path for their tiles, and
+// so do the items that would widen the launch's box past the budget.
 void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const TileCfg *const force[2], BatchBuild &b)
 {
     b.groups.clear();
@@ -224,6 +270,7 @@ void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const Til
             stage.push_back(op == OP_RESIZE ? !wants_gather(j, op) && (double)j.sw < 2.0 * (double)j.dw &&
                                                   fits(j, op, P, KB_LDS_BUDGET)
                                             : fits(j, op, P, KB_LDS_BUDGET));
+        fit_launch_box(imgs[k], op, cfg_tw(P), cfg_th(P), KB_LDS_BUDGET, stage);
         b.groups.emplace_back();
         b.tables.emplace_back();
         build_group(op, P, f32, c, imgs[k], stage, b.groups.back(), b.tables.back());
