@@ -38,6 +38,9 @@
  *    (U8, F32), (F32, F32).  norm is only accepted with an F32 destination.
  *    For a U8 source the border value must be an integer in [0, 255].
  *  - All entry points are reentrant; no C++ exception crosses the ABI.
+ *  - Outputs are written with non-temporal stores: they go to HBM rather than
+ *    staying in the GPU caches, so a kernel that reads them next fetches them
+ *    from HBM (the bits are the same either way).
  */
 #ifndef KR_H
 #define KR_H
