@@ -39,7 +39,7 @@ def kernel_source_sha() -> str:
     return source_sha()
 
 
-_TPL = re.compile(r"kr::k_(tiled_ws|tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"
+_TPL = re.compile(r"kr::k_(tiled|batch)<(\d+), (\d+), (true|false), (\d+), (\d+), (\d+), (\d+), \d+"
                   r"(?:, (?:true|false))?>")
 _OPS = {"0": "resize", "1": "warp", "2": "perspective"}
 _POINT = re.compile(r"kr::(?:\(anonymous namespace\)::)?k_(nearest|flip_u8|flip_f32|gray|half|permute)<([^>]*)>")
@@ -55,7 +55,7 @@ def label(name: str) -> str:
     if m:
         kind, op, c, f32, px, txt, cpt, rpt = m.groups()
         dt = "f32" if f32 == "true" else "u8"
-        pre = {"batch": "batch_", "tiled_ws": "ws_"}.get(kind, "")
+        pre = "batch_" if kind == "batch" else ""
         return f"{pre}{_OPS[op]}_{dt} c{c} {px}x{txt}x{cpt}x{rpt}"
     if "k_copy" in name:
         return "copy"
