@@ -4,8 +4,9 @@
 //
 // Each slot owns a stream, a completion event, a pinned host staging buffer
 // and a device buffer for its batch's work-list, all created once.  A slot's
-// batch is launched with one-tile-per-block grids so that batches of
-// different slots share the GPU.  A slot is reused only after its event has
+// batch takes its class's batch configuration (one workgroup per tile unless
+// the tuning table names a persistent grid), so that batches of different
+// slots share the GPU.  A slot is reused only after its event has
 // completed, so its staging and work-list buffers are never overwritten while
 // in flight.  Output blocks stay allocated until released by the caller.
 // One server object is driven by one host thread at a time.

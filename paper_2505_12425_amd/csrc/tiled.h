@@ -836,8 +836,7 @@ __device__ __noinline__ void write_tail_group(uint32_t *d, const uint8_t *src, i
 }
 
 // Issue the loads of this thread's first MAXIT work items of a tile.  The
-// staging threads are numbered lt = 0 .. NLT - 1: the whole workgroup, or
-// the loader wave of a wave-specialised workgroup.
+// staging threads are numbered lt = 0 .. NLT - 1 (the whole workgroup).
 template <int OP, int C, int MAXIT, int NLT = KT_THREADS>
 __device__ __forceinline__ void prefetch(const TiledJob &t, const Plan &p, const TileGeom &G, Prefetch<C, MAXIT> &pf,
                                          int lt)
