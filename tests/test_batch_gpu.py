@@ -191,6 +191,38 @@ def test_warp_batch_all_lds_classes(out):
                              f"item {i}")
 
 
+@pytest.mark.parametrize("out", ["u8", "f32"])
+def test_warp_batch_launch_box_budget(out):
+    """Warps whose boxes each fit the batch LDS budget but not together: at a
+    0.7x shrink the default 64x16 tiles need wide boxes at 0 degrees and tall
+    ones at 90 degrees, and the launch's box (widest pitch times most rows)
+    would exceed the budget, so the tall ones move to the gather path.  Every
+    item equals its single call bitwise and the oracle."""
+    dt = torch.uint8 if out == "u8" else torch.float32
+    specs, refs = [], []
+    for i, theta in enumerate([0.0, 90.0, 0.0, 90.0, 2.0, 88.0]):
+        h, w = 260 + 6 * i, 340 + 10 * i
+        im = wl.uniform_u8(h, w, 3, seed=500 + i)
+        m = wl.affine_compose(h, w, theta, 0.7, 0.0, 3.0 * i, -2.0 * i)
+        specs.append({"op": "warp", "src": torch.from_numpy(im).cuda(), "m": m,
+                      "dst": torch.empty((h, w, 3), dtype=dt, device="cuda")})
+        refs.append((im, m, h, w))
+    say(f"warp batch, launch box over the budget, out={out}")
+    kr.resize_batch(specs, border=kr.CONSTANT, border_value=5)
+    torch.cuda.synchronize()
+    for i, (sp, (im, m, dh, dw)) in enumerate(zip(specs, refs)):
+        got = sp["dst"].cpu().numpy()
+        single = _single(sp, border=kr.CONSTANT, border_value=5)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy(), got), f"item {i}: batch != single"
+        if out == "u8":
+            assert_u8_equal(got, oracle.warp(im, m, dh, dw, "u8", border=oracle.CONSTANT, bval=5, threads=TH),
+                            f"item {i}")
+        else:
+            assert_f32_close(got, oracle.warp(im, m, dh, dw, "f64", border=oracle.CONSTANT, bval=5, threads=TH),
+                             f"item {i}")
+
+
 @pytest.mark.parametrize("c,out", [(3, "f32"), (3, "u8"), (4, "u8"), (4, "f32")])
 def test_planar_layout_equals_interleaved(c, out):
     """CHW destinations hold exactly the HWC results, transposed, for a mixed
