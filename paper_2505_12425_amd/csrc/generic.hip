@@ -1,9 +1,9 @@
 // generic.hip -- one-thread-per-pixel bilinear resize / warp kernels.
 //
 // These evaluate the resampling definition directly: every tap is read from
-// global memory with its own border test.  They cover every channel count,
-// dtype pair and matrix, and serve as the fallback for the tiled kernels
-// when a warp's inverse-mapped footprint does not fit in LDS.
+// global memory with its own border test.  They serve f32 sources (every
+// channel count and matrix); u8 sources run on the LDS-tiled kernels, whose
+// global-gather path takes the tiles whose footprint does not fit in LDS.
 //
 // Coordinate rules (the paper prints none; these are the fixed readings):
 //  * resize: half-pixel centres, source x = ((2 dx + 1) W_in - W_out) / (2 W_out)
@@ -45,10 +45,8 @@ template <int C>
 static hipError_t launch_generic_c(int op, kr_dtype st, kr_dtype dt, const ImageJob &j,
                                    const Epilogue &e, hipStream_t s)
 {
-    if (st == KR_U8 && dt == KR_U8)
-        return launch_generic_t<C, uint8_t, uint8_t>(op, j, e, s);
-    if (st == KR_U8 && dt == KR_F32)
-        return launch_generic_t<C, uint8_t, float>(op, j, e, s);
+    if (st != KR_F32 || dt != KR_F32)
+        return hipErrorNotSupported;  // u8 sources: the tiled kernels
     return launch_generic_t<C, float, float>(op, j, e, s);
 }
 

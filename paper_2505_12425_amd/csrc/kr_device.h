@@ -98,27 +98,6 @@ __device__ __forceinline__ float blend4(float p00, float p01, float p10, float p
     return __builtin_fmaf(w.w11, p11, __builtin_fmaf(w.w10, p10, __builtin_fmaf(w.w01, p01, w.w00 * p00)));
 }
 
-// One tap of C channels as integers (u8 source) with the border rule.
-template <int C, typename S>
-__device__ __forceinline__ void tap_int(const S *src, const ImageJob &j, int x, int y, const Epilogue &e, int (&p)[C])
-{
-    const int h = j.sh, w = j.sw;
-    if ((unsigned)x >= (unsigned)w || (unsigned)y >= (unsigned)h) {
-        if (e.border == KR_BORDER_CONSTANT) {
-#pragma unroll
-            for (int c = 0; c < C; c++)
-                p[c] = e.bval_i;
-            return;
-        }
-        x = x < 0 ? 0 : (x >= w ? w - 1 : x);
-        y = y < 0 ? 0 : (y >= h ? h - 1 : y);
-    }
-    const S *q = src + ((size_t)j.sk + (size_t)y * (size_t)j.sp + (size_t)x) * C;
-#pragma unroll
-    for (int c = 0; c < C; c++)
-        p[c] = (int)q[c];
-}
-
 // One tap of C channels as floats with the border rule.
 template <int C, typename S>
 __device__ __forceinline__ void tap_float(const S *src, const ImageJob &j, int x, int y, const Epilogue &e, float (&p)[C])
@@ -140,8 +119,8 @@ __device__ __forceinline__ void tap_float(const S *src, const ImageJob &j, int x
         p[c] = (float)q[c];
 }
 
-// One output pixel (x, y) evaluated straight from the definition: every tap
-// read from global memory with its own border test.
+// One output pixel (x, y) of an f32 source evaluated straight from the
+// definition: every tap read from global memory with its own border test.
 template <int C, typename S, typename D, int OP>
 __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue &e, int x, int y)
 {
@@ -166,39 +145,16 @@ __device__ __forceinline__ void generic_pixel(const ImageJob &j, const Epilogue 
     }
     const S *src = static_cast<const S *>(j.src);
     D *dst = static_cast<D *>(j.dst) + ((size_t)y * (size_t)j.dw + (size_t)x) * C;
-    if constexpr (is_u8<D>::value) {
-        const int wx[2] = {2048 - wx1, wx1};
-        const int wy[2] = {2048 - wy1, wy1};
-        int acc[C];
+    static_assert(!is_u8<D>::value, "u8 outputs come from u8 sources, which the tiled kernels take");
+    const Weights2 w = weights2(1.0f - fx, fx, 1.0f - fy, fy);
+    float p00[C], p01[C], p10[C], p11[C];
+    tap_float<C>(src, j, x0, y0, e, p00);
+    tap_float<C>(src, j, x0 + 1, y0, e, p01);
+    tap_float<C>(src, j, x0, y0 + 1, e, p10);
+    tap_float<C>(src, j, x0 + 1, y0 + 1, e, p11);
 #pragma unroll
-        for (int c = 0; c < C; c++)
-            acc[c] = 0;
-#pragma unroll
-        for (int i = 0; i < 2; i++) {
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                const int w = wy[i] * wx[k];
-                int p[C];
-                tap_int<C>(src, j, x0 + k, y0 + i, e, p);
-#pragma unroll
-                for (int c = 0; c < C; c++)
-                    acc[c] += w * p[c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < C; c++)
-            dst[c] = (uint8_t)((acc[c] + (1 << 21)) >> 22);
-    } else {
-        const Weights2 w = weights2(1.0f - fx, fx, 1.0f - fy, fy);
-        float p00[C], p01[C], p10[C], p11[C];
-        tap_float<C>(src, j, x0, y0, e, p00);
-        tap_float<C>(src, j, x0 + 1, y0, e, p01);
-        tap_float<C>(src, j, x0, y0 + 1, e, p10);
-        tap_float<C>(src, j, x0 + 1, y0 + 1, e, p11);
-#pragma unroll
-        for (int c = 0; c < C; c++)
-            dst[c] = __builtin_fmaf(blend4(p00[c], p01[c], p10[c], p11[c], w), e.alpha[c], e.beta[c]);
-    }
+    for (int c = 0; c < C; c++)
+        dst[c] = __builtin_fmaf(blend4(p00[c], p01[c], p10[c], p11[c], w), e.alpha[c], e.beta[c]);
 }
 
 }  // namespace kr

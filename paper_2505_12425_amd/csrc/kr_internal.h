@@ -65,7 +65,7 @@ hipError_t launch_permute(int c, kr_dtype dt, const ImageJob &j, const int (&m)[
 // Resize of an RGB u8 source to one gray channel (e.gray set): the exact-2x
 // kernel where it applies, the LDS-tiled kernel otherwise.
 hipError_t launch_resize_gray(kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
-// The LDS-tiled kernels (u8 sources with 3 or 4 channels) directly.
+// The LDS-tiled kernels (u8 sources, 1-4 channels) directly.
 hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Traffic-mix probe: shrink > 0 reads 2^shrink input chunks per output chunk,

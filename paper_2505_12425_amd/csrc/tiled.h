@@ -270,7 +270,11 @@ __device__ __forceinline__ void resize_axis_r(int d, int n_in, int n_out, double
 template <int C>
 __device__ __forceinline__ uint32_t pack_px(const uint32_t (&v)[C])
 {
-    if constexpr (C == 3)
+    if constexpr (C == 1)
+        return v[0] >> 24;
+    else if constexpr (C == 2)
+        return __builtin_amdgcn_perm(v[1], v[0], 0x0C0C0703u);
+    else if constexpr (C == 3)
         return __builtin_amdgcn_perm(v[2], __builtin_amdgcn_perm(v[1], v[0], 0x0C0C0703u), 0x0C070100u);
     else
         return __builtin_amdgcn_perm(v[3], v[2], 0x07030C0Cu) | __builtin_amdgcn_perm(v[1], v[0], 0x0C0C0703u);
@@ -306,12 +310,14 @@ __device__ __forceinline__ void store_u8_4(uint8_t *p, int n, bool aligned, cons
         } else if constexpr (C == 4) {
             __builtin_nontemporal_store(u32x4{P[0], P[1], P[2], P[3]}, reinterpret_cast<u32x4 *>(p));
         } else if constexpr (C == 2) {
-            *reinterpret_cast<u32x2 *>(p) = u32x2{__builtin_amdgcn_perm(P[1], P[0], 0x05040100u),
-                                                 __builtin_amdgcn_perm(P[3], P[2], 0x05040100u)};
+            __builtin_nontemporal_store(u32x2{__builtin_amdgcn_perm(P[1], P[0], 0x05040100u),
+                                              __builtin_amdgcn_perm(P[3], P[2], 0x05040100u)},
+                                        reinterpret_cast<u32x2 *>(p));
         } else {
-            *reinterpret_cast<uint32_t *>(p) =
+            __builtin_nontemporal_store(
                 __builtin_amdgcn_perm(__builtin_amdgcn_perm(P[3], P[2], 0x0C0C0400u),
-                                      __builtin_amdgcn_perm(P[1], P[0], 0x0C0C0400u), 0x05040100u);
+                                      __builtin_amdgcn_perm(P[1], P[0], 0x0C0C0400u), 0x05040100u),
+                reinterpret_cast<uint32_t *>(p));
         }
     } else {
         for (int k = 0; k < n; k++)
@@ -756,8 +762,8 @@ __device__ __forceinline__ int slot_row(const TiledJob &t, const Plan &p, int s)
 // ------------------------------------------------------------------ staging
 // Box rows are staged as one dword per pixel.  Work item k covers one
 // 16-pixel group (aligned on the image's linear pixel index) of one slot:
-// 48 (RGB) or 64 (RGBA) contiguous, 16-byte aligned source bytes.
-template <int C> struct GroupRegs { u32x4 q[C == 3 ? 3 : 4]; };
+// 16 C contiguous, 16-byte aligned source bytes (48 for RGB, 64 for RGBA).
+template <int C> struct GroupRegs { u32x4 q[C]; };
 
 template <int C, int MAXIT> struct Prefetch {
     GroupRegs<C> g[MAXIT];
@@ -794,15 +800,32 @@ __device__ __forceinline__ void load_group(const uint8_t *__restrict__ src, int 
 {
     const u32x4 *q = reinterpret_cast<const u32x4 *>(src + (size_t)p0 * C);
 #pragma unroll
-    for (int i = 0; i < (C == 3 ? 3 : 4); i++)
+    for (int i = 0; i < C; i++)
         r.q[i] = q[i];
 }
 
-// Widen a loaded group to 16 pixel dwords in LDS (RGB: byte 3 is unspecified).
+// Widen a loaded group to 16 pixel dwords in LDS (bytes past a pixel's C
+// channels are unspecified: those of the next pixels, or zero).
 template <int C>
 __device__ __forceinline__ void write_group(uint32_t *d, const GroupRegs<C> &r)
 {
-    if constexpr (C == 3) {
+    if constexpr (C == 1) {
+        const uint32_t w[4] = {r.q[0].x, r.q[0].y, r.q[0].z, r.q[0].w};
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            d[4 * t + 0] = w[t];
+            d[4 * t + 1] = w[t] >> 8;
+            d[4 * t + 2] = w[t] >> 16;
+            d[4 * t + 3] = w[t] >> 24;
+        }
+    } else if constexpr (C == 2) {
+        const uint32_t w[8] = {r.q[0].x, r.q[0].y, r.q[0].z, r.q[0].w, r.q[1].x, r.q[1].y, r.q[1].z, r.q[1].w};
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            d[2 * t + 0] = w[t];
+            d[2 * t + 1] = w[t] >> 16;
+        }
+    } else if constexpr (C == 3) {
         const uint32_t w[12] = {r.q[0].x, r.q[0].y, r.q[0].z, r.q[0].w, r.q[1].x, r.q[1].y,
                                 r.q[1].z, r.q[1].w, r.q[2].x, r.q[2].y, r.q[2].z, r.q[2].w};
 #pragma unroll
@@ -1255,8 +1278,8 @@ __device__ __forceinline__ void compute_resize(const TiledJob &t, const Plan &p,
 // down-sampling ratios, where neighbouring outputs share no taps) read their
 // taps straight from global memory: per tap row, the two horizontal taps are
 // 2 * C contiguous bytes, loaded as one dword-aligned 12-byte (RGB) or 8-byte
-// (RGBA) read and realigned with byte-align ops.  Taps outside the image take
-// the border rule per tap.
+// (RGBA) read and realigned with byte-align ops (one and two channels: byte
+// by byte).  Taps outside the image take the border rule per tap.
 
 // The two horizontal taps at (x0, y) and (x0 + 1, y), both inside the image,
 // as pixel dwords (byte c = channel c; RGB byte 3 unspecified).
@@ -1269,6 +1292,10 @@ __device__ __forceinline__ void load_tap_pair(const uint8_t *__restrict__ src, s
         const D2 d = *reinterpret_cast<const D2 *>(src + lin * 4);
         t0 = d.a;
         t1 = d.b;
+    } else if constexpr (C < 3) {
+        (void)nbytes;
+        t0 = load_px_bytes<C>(src, lin);
+        t1 = load_px_bytes<C>(src, lin + 1);
     } else {
         const size_t b = lin * 3;
         const size_t f = b & ~(size_t)3;

@@ -289,14 +289,16 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
     fits = lds <= KT_LDS_CAP;
     if (!fits)
         return hipSuccess;
-    if (mode == GRID_PERSISTENT) {
-        auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_PERS, true>;
-        const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), lds));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
-    } else {
-        auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, false>;
-        hipLaunchKernelGGL(kern, dim3(t.ntiles), dim3(KT_THREADS), lds, s, t, e, G);
+    if constexpr (C >= 3) {  // one- and two-channel sources: one workgroup per tile
+        if (mode == GRID_PERSISTENT) {
+            auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_PERS, true>;
+            const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), lds));
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), lds, s, t, e, G);
+            return hipGetLastError();
+        }
     }
+    auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT, false>;
+    hipLaunchKernelGGL(kern, dim3(t.ntiles), dim3(KT_THREADS), lds, s, t, e, G);
     return hipGetLastError();
 }
 
@@ -307,7 +309,13 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 #define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
     if (cfg.px == PX && cfg.txt == TXT && cfg.cpt == CPT && cfg.rpt == RPT)                              \
         return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.grid, gather, fits);
-    if constexpr (OP != OP_RESIZE) {
+    if constexpr (C < 3) {
+        if constexpr (OP != OP_RESIZE) {
+            KR_WARP_CFGS_NARROW(KR_TRY)
+        } else {
+            KR_RESIZE_CFGS_NARROW(KR_TRY)
+        }
+    } else if constexpr (OP != OP_RESIZE) {
         KR_WARP_CFGS(KR_TRY)
     } else {
         KR_RESIZE_CFGS(KR_TRY)
@@ -320,8 +328,9 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 // Tile shapes tried in order (the first whose LDS footprint fits is used).
 // KR_TILE="PXxTXTxCPTxRPT" and KR_GRID="full"|"persistent" override the
 // first choice.  gather: a resize whose taps are read from global memory
-// (it shrinks x by more than 3).
-static int default_cfgs(int op, bool f32, bool gather, TileCfg *out)
+// (it shrinks x by more than 3).  narrow: a one- or two-channel source
+// (4-pixel runs, one workgroup per tile).
+static int default_cfgs(int op, bool f32, bool gather, bool narrow, TileCfg *out)
 {
     int n = 0;
     const char *tile = std::getenv("KR_TILE");
@@ -336,6 +345,15 @@ static int default_cfgs(int op, bool f32, bool gather, TileCfg *out)
     auto add = [&](int a, int b, int c, int d, bool pers) {
         out[n++] = TileCfg{a, b, c, d, force >= 0 ? force : (pers ? GRID_PERSISTENT : GRID_FULL)};
     };
+    if (narrow) {
+        if (op != OP_RESIZE) {
+            add(4, 16, 1, 2, false);
+            add(4, 8, 1, 1, false);
+        } else {
+            add(4, gather ? 64 : 16, 1, 1, false);
+        }
+        return n;
+    }
     // the autotuner's choices on MI355X for 4K sources (3840x2160x3 u8, every
     // source read from HBM): f32 warps run best on a persistent grid of 16-row
     // columns, u8 warps and resizes with one workgroup per tile
@@ -369,7 +387,7 @@ static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
     TileCfg tuned;
     if (tune_lookup(tune_key_image(OP, C, F32, j), &tuned))
         cfgs[n++] = tuned;
-    n += default_cfgs(OP, F32, wants_gather(j, OP), cfgs + n);
+    n += default_cfgs(OP, F32, wants_gather(j, OP), C < 3, cfgs + n);
     for (int i = 0; i < n; i++) {
         bool fits = false;
         const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, false, fits);
@@ -408,22 +426,31 @@ hipError_t launch_tiled_cfg(int op, int c, kr_dtype dt, const TileCfg &cfg, cons
 
 bool tiled_supported(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 4); }
 
+bool tiled_image_supported(int c, kr_dtype st) { return st == KR_U8 && c >= 1 && c <= 4; }
+
+template <int OP>
+static hipError_t launch_op(int c, bool f, const ImageJob &j, const Epilogue &e, hipStream_t s)
+{
+    switch (c) {
+    case 1:
+        return f ? launch_c<OP, 1, true>(j, e, s) : launch_c<OP, 1, false>(j, e, s);
+    case 2:
+        return f ? launch_c<OP, 2, true>(j, e, s) : launch_c<OP, 2, false>(j, e, s);
+    case 3:
+        return f ? launch_c<OP, 3, true>(j, e, s) : launch_c<OP, 3, false>(j, e, s);
+    default:
+        return f ? launch_c<OP, 4, true>(j, e, s) : launch_c<OP, 4, false>(j, e, s);
+    }
+}
+
 hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
     const bool f = dt == KR_F32;
-    if (op == OP_PERSP) {
-        if (c == 3)
-            return f ? launch_c<OP_PERSP, 3, true>(j, e, s) : launch_c<OP_PERSP, 3, false>(j, e, s);
-        return f ? launch_c<OP_PERSP, 4, true>(j, e, s) : launch_c<OP_PERSP, 4, false>(j, e, s);
-    }
-    if (op == OP_WARP) {
-        if (c == 3)
-            return f ? launch_c<OP_WARP, 3, true>(j, e, s) : launch_c<OP_WARP, 3, false>(j, e, s);
-        return f ? launch_c<OP_WARP, 4, true>(j, e, s) : launch_c<OP_WARP, 4, false>(j, e, s);
-    }
-    if (c == 3)
-        return f ? launch_c<OP_RESIZE, 3, true>(j, e, s) : launch_c<OP_RESIZE, 3, false>(j, e, s);
-    return f ? launch_c<OP_RESIZE, 4, true>(j, e, s) : launch_c<OP_RESIZE, 4, false>(j, e, s);
+    if (op == OP_PERSP)
+        return launch_op<OP_PERSP>(c, f, j, e, s);
+    if (op == OP_WARP)
+        return launch_op<OP_WARP>(c, f, j, e, s);
+    return launch_op<OP_RESIZE>(c, f, j, e, s);
 }
 
 }  // namespace kr

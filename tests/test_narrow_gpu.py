@@ -1,0 +1,116 @@
+"""GPU parity of one- and two-channel u8 sources, which run on the LDS-tiled
+kernels (one workgroup per tile, runs of 4 pixels per lane): warps over the
+shapes of the RGB parity cases (rotations, shrinks, zooms, tiles that are all
+border), resizes that stage boxes or gather their taps from global memory,
+perspective warps, views into larger buffers, normalised outputs and a 4K
+warp, each against the oracle (u8 bit-exact, f32 within 1e-3 absolute on the
+0..255 scale)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_12425_amd import workloads as wl
+from tests.gpu_util import assert_f32_close, assert_u8_equal, dev, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2505_12425_amd import kr  # noqa: E402
+from tests.test_parity_gpu import WARPS, check_resize, check_warp  # noqa: E402
+
+CONST, REPL = 0, 1
+TH = 8
+
+
+@pytest.mark.parametrize("c", [1, 2])
+@pytest.mark.parametrize("k", range(len(WARPS)))
+@pytest.mark.parametrize("border,bval", [(CONST, 200), (REPL, 0)])
+def test_narrow_warp_shapes(c, k, border, bval):
+    h, w, dh, dw, th, s, sh, tx, ty = WARPS[k]
+    img = wl.uniform_u8(h, w, c, seed=100 + 10 * k + c)
+    m = wl.affine_compose(h, w, th, s, sh, tx, ty)
+    check_warp(img, m, dh, dw, border, bval, what=f"narrow c={c} case {k}")
+
+
+@pytest.mark.parametrize("c", [1, 2])
+@pytest.mark.parametrize("shape", [(123, 77, 250, 160), (1080, 1920, 700, 1000), (300, 410, 47, 1201),
+                                   (2160, 240, 224, 224), (31, 1, 7, 45), (5, 900, 900, 5)])
+@pytest.mark.parametrize("border,bval", [(CONST, 17), (REPL, 0)])
+def test_narrow_resize_shapes(c, shape, border, bval):
+    h, w, dh, dw = shape
+    img = wl.uniform_u8(h, w, c, seed=h + w + c)
+    check_resize(img, dh, dw, border, bval, what=f"narrow c={c}")
+
+
+@pytest.mark.parametrize("c", [1, 2])
+def test_narrow_normalised(c):
+    img = wl.mixed_u8(333, 517, c, seed=7 + c)
+    mean, std = (0.45, 0.5)[:c], (0.226, 0.25)[:c]
+    m = wl.affine_compose(333, 517, -21.0, 0.8, 0.05, 9.0, -4.0)
+    say(f"narrow normalised c={c}")
+    d = torch.empty((300, 480, c), dtype=torch.float32, device="cuda")
+    kr.warp_affine(dev(img), d, m, border=CONST, border_value=5.0, mean=mean, std=std)
+    torch.cuda.synchronize()
+    assert_f32_close(d.cpu().numpy(), oracle.warp(img, m, 300, 480, "f64", False, CONST, 5.0, mean, std, threads=TH),
+                     "narrow warp norm", std=std)
+    d = torch.empty((211, 390, c), dtype=torch.float32, device="cuda")
+    kr.resize(dev(img), d, border=REPL, mean=mean, std=std)
+    torch.cuda.synchronize()
+    assert_f32_close(d.cpu().numpy(), oracle.resize(img, 211, 390, "f64", REPL, 0, mean, std, threads=TH),
+                     "narrow resize norm", std=std)
+
+
+@pytest.mark.parametrize("c", [1, 2])
+def test_narrow_views(c):
+    """Crops of a larger buffer (odd offsets, the parent's first and last
+    pixels): the staged groups start before and end after the view, and the
+    last pixels of the view are read byte by byte."""
+    par = wl.uniform_u8(260, 700, c, seed=31 + c)
+    dev_par = dev(par)
+    m = wl.affine_compose(100, 200, 12.0, 1.05, 0.0, 2.0, 1.0)
+    for (y, x, h, w) in ((1, 3, 100, 200), (0, 0, 260, 700), (160, 500, 100, 200), (7, 13, 33, 41)):
+        view = dev_par[y:y + h, x:x + w]
+        host = np.ascontiguousarray(par[y:y + h, x:x + w])
+        for out in ("u8", "f32"):
+            say(f"narrow view c={c} {y},{x},{h}x{w} {out}")
+            dt = torch.uint8 if out == "u8" else torch.float32
+            dw_ = torch.empty((90, 170, c), dtype=dt, device="cuda")
+            kr.warp_affine(view, dw_, m, border=REPL)
+            dr = torch.empty((57, 311, c), dtype=dt, device="cuda")
+            kr.resize(view, dr, border=CONST, border_value=3.0)
+            torch.cuda.synchronize()
+            ew = oracle.warp(host, m, 90, 170, "u8" if out == "u8" else "f64", False, REPL, 0, threads=TH)
+            er = oracle.resize(host, 57, 311, "u8" if out == "u8" else "f64", CONST, 3.0, threads=TH)
+            if out == "u8":
+                assert_u8_equal(dw_.cpu().numpy(), ew, "narrow view warp")
+                assert_u8_equal(dr.cpu().numpy(), er, "narrow view resize")
+            else:
+                assert_f32_close(dw_.cpu().numpy(), ew, "narrow view warp f32")
+                assert_f32_close(dr.cpu().numpy(), er, "narrow view resize f32")
+
+
+@pytest.mark.parametrize("c", [1, 2])
+def test_narrow_perspective(c):
+    img = wl.uniform_u8(240, 320, c, seed=70 + c)
+    m9 = np.array([[0.9, 0.08, 12.0], [-0.05, 1.1, 4.0], [2e-4, -1e-4, 1.0]])
+    for border, bval in ((CONST, 99), (REPL, 0)):
+        for out in ("u8", "f32"):
+            say(f"narrow perspective c={c} border={border} {out}")
+            d = torch.empty((250, 300, c), dtype=torch.uint8 if out == "u8" else torch.float32, device="cuda")
+            kr.warp_perspective(dev(img), d, m9, border=border, border_value=float(bval))
+            torch.cuda.synchronize()
+            exp = oracle.warp_perspective(img, m9, 250, 300, "u8" if out == "u8" else "f64", False, border, bval,
+                                          threads=TH)
+            if out == "u8":
+                assert_u8_equal(d.cpu().numpy(), exp, "narrow perspective")
+            else:
+                assert_f32_close(d.cpu().numpy(), exp, "narrow perspective f32")
+
+
+def test_narrow_4k_warp():
+    img = wl.mixed_u8(2160, 3840, 1, seed=0)
+    check_warp(img, wl.random_affine_4k(2160, 3840, 0), 2160, 3840, CONST, 0, what="4K gray seed 0")

@@ -10,10 +10,9 @@ essentially never tie, so these cases are chosen to tie everywhere (the tie
 counts are asserted on the host, in exact integers, before the GPU runs), with
 both parities of k, so that rounding up and rounding down are both exercised.
 
-Paths covered: the LDS-tiled kernel (C = 3, 4: the integer rule of its resize
+Paths covered: the LDS-tiled kernel (C = 1-4: the integer rule of its resize
 tables and the magic-constant rounding of its 2048-scaled warp coordinates),
-its global-gather path (x shrink above 3), the per-pixel kernel (C = 1, 2:
-rint in binary64), the perspective kernels (tiled and per-pixel), and batch
+its global-gather path (x shrink above 3), the perspective kernels, and batch
 items (u8 bit-exact against the oracle and against the single-image call).
 """
 from __future__ import annotations
