@@ -260,7 +260,7 @@ size_t kr_resize_batch_workspace_size(int n);
  * caller and not touched by other work until the batch completes.  Each
  * item's output is bit-identical to the single-image call on the same item.
  * Destinations must not overlap each other or any source.  Batched launches
- * take u8 sources with 3 or 4 channels (KR_ERR_UNSUPPORTED otherwise).
+ * take u8 sources with 1-4 channels (KR_ERR_UNSUPPORTED otherwise).
  */
 kr_status kr_resize_batch(const kr_batch_item *items, int n, int c, kr_dtype src_t, kr_dtype dst_t,
                           kr_border border, float border_value, const kr_normalize *norm,
@@ -424,7 +424,8 @@ void kr_server_destroy(kr_server *server);
  * is read from HBM and the previous output is written back, as in a stream
  * of distinct images; the time of the overwrites alone is subtracted.
  * Only u8 sources with 3 or 4 channels have configurations
- * (KR_ERR_UNSUPPORTED otherwise).
+ * (KR_ERR_UNSUPPORTED otherwise; one- and two-channel sources run fixed
+ * configurations).
  * kr_autotune_batch: same arguments as kr_resize_batch plus reps, scrub and
  * report; tunes the resize and the warp launch of the batch separately.
  * kr_autotune_save: writes the table as text into buf (truncated to len

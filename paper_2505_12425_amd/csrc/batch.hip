@@ -58,16 +58,18 @@ static hipError_t launch_group_cfg(const BatchGroup &g, const Epilogue &e, hipSt
     int widest = 0;  // largest per-XCD tile range
     for (int k = 0; k < 8; k++)
         widest = std::max(widest, g.bins.start[k + 1] - g.bins.start[k]);
-    if (g.cfg.grid == GRID_PERSISTENT) {
-        auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 1, true>;
-        const long resident = (long)blocks_per_cu(reinterpret_cast<const void *>(kern), g.lds) * device_cus();
-        const int grid = (int)std::max(8L, std::min(8L * widest, resident & ~7L));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.bins, e, g.G);
-    } else {
-        auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 3, false>;
-        hipLaunchKernelGGL(kern, dim3(8 * std::max(widest, 1)), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs,
-                           g.bins, e, g.G);
+    if constexpr (C >= 3) {  // one- and two-channel sources: one workgroup per tile
+        if (g.cfg.grid == GRID_PERSISTENT) {
+            auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 1, true>;
+            const long resident = (long)blocks_per_cu(reinterpret_cast<const void *>(kern), g.lds) * device_cus();
+            const int grid = (int)std::max(8L, std::min(8L * widest, resident & ~7L));
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.bins, e, g.G);
+            return hipGetLastError();
+        }
     }
+    auto kern = k_batch<OP, C, F32, PX, TXT, CPT, RPT, 3, false>;
+    hipLaunchKernelGGL(kern, dim3(8 * std::max(widest, 1)), dim3(KT_THREADS), g.lds, s, g.jobs_dev, g.njobs, g.bins,
+                       e, g.G);
     return hipGetLastError();
 }
 
@@ -77,7 +79,13 @@ static hipError_t launch_group_c(const BatchGroup &g, const Epilogue &e, hipStre
 #define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
     if (g.cfg.px == PX && g.cfg.txt == TXT && g.cfg.cpt == CPT && g.cfg.rpt == RPT)                      \
         return launch_group_cfg<OP, C, F32, PX, TXT, CPT, RPT>(g, e, s);
-    if constexpr (OP == OP_WARP) {
+    if constexpr (C < 3) {
+        if constexpr (OP == OP_WARP) {
+            KR_BATCH_WARP_CFGS_NARROW(KR_TRY)
+        } else {
+            KR_BATCH_RESIZE_CFGS_NARROW(KR_TRY)
+        }
+    } else if constexpr (OP == OP_WARP) {
         KR_BATCH_WARP_CFGS(KR_TRY)
     } else {
         KR_BATCH_RESIZE_CFGS(KR_TRY)
@@ -86,19 +94,27 @@ static hipError_t launch_group_c(const BatchGroup &g, const Epilogue &e, hipStre
     return hipErrorInvalidValue;
 }
 
+template <int OP>
+static hipError_t launch_group_op(const BatchGroup &g, int c, bool f, const Epilogue &e, hipStream_t s)
+{
+    switch (c) {
+    case 1:
+        return f ? launch_group_c<OP, 1, true>(g, e, s) : launch_group_c<OP, 1, false>(g, e, s);
+    case 2:
+        return f ? launch_group_c<OP, 2, true>(g, e, s) : launch_group_c<OP, 2, false>(g, e, s);
+    case 3:
+        return f ? launch_group_c<OP, 3, true>(g, e, s) : launch_group_c<OP, 3, false>(g, e, s);
+    default:
+        return f ? launch_group_c<OP, 4, true>(g, e, s) : launch_group_c<OP, 4, false>(g, e, s);
+    }
+}
+
 hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue &e, hipStream_t s)
 {
     if (g.njobs == 0)
         return hipSuccess;
     const bool f = dt == KR_F32;
-    if (g.op == OP_WARP) {
-        if (c == 3)
-            return f ? launch_group_c<OP_WARP, 3, true>(g, e, s) : launch_group_c<OP_WARP, 3, false>(g, e, s);
-        return f ? launch_group_c<OP_WARP, 4, true>(g, e, s) : launch_group_c<OP_WARP, 4, false>(g, e, s);
-    }
-    if (c == 3)
-        return f ? launch_group_c<OP_RESIZE, 3, true>(g, e, s) : launch_group_c<OP_RESIZE, 3, false>(g, e, s);
-    return f ? launch_group_c<OP_RESIZE, 4, true>(g, e, s) : launch_group_c<OP_RESIZE, 4, false>(g, e, s);
+    return g.op == OP_WARP ? launch_group_op<OP_WARP>(g, c, f, e, s) : launch_group_op<OP_RESIZE>(g, c, f, e, s);
 }
 
 // LDS per workgroup of a batch launch.  Every workgroup of the launch takes
@@ -112,11 +128,12 @@ hipError_t launch_group(const BatchGroup &g, int c, kr_dtype dt, const Epilogue 
 constexpr size_t KB_LDS_BUDGET = 32 * 1024;
 
 // Tile shape of a batch group when the batch class is not tuned: small
-// tiles, so that batches of small outputs still produce many tiles.
-static TileCfg default_batch_cfg(int op, bool f32)
+// tiles, so that batches of small outputs still produce many tiles
+// (one- and two-channel sources: 4-pixel runs).
+static TileCfg default_batch_cfg(int op, bool f32, int c)
 {
     (void)op;
-    return f32 ? TileCfg{1, 64, 1, 4, GRID_FULL} : TileCfg{4, 16, 1, 1, GRID_FULL};
+    return f32 && c >= 3 ? TileCfg{1, 64, 1, 4, GRID_FULL} : TileCfg{4, 16, 1, 1, GRID_FULL};
 }
 
 static int cfg_tw(const TileCfg &c) { return c.txt * c.px * c.cpt; }
@@ -259,12 +276,14 @@ void build_batch(const std::vector<ImageJob> imgs[2], bool f32, int c, const Til
             continue;
         const int op = k == 0 ? OP_RESIZE : OP_WARP;
         TileCfg P, tuned;
-        if (force[k])
+        if (c < 3)  // untuned: the configurations compiled for them
+            P = default_batch_cfg(op, f32, c);
+        else if (force[k])
             P = *force[k];
         else if (tune_lookup(tune_key_batch(op, c, f32, imgs[k]), &tuned))
             P = tuned;
         else
-            P = default_batch_cfg(op, f32);
+            P = default_batch_cfg(op, f32, c);
         std::vector<bool> stage;
         for (const ImageJob &j : imgs[k])
             stage.push_back(op == OP_RESIZE ? !wants_gather(j, op) && (double)j.sw < 2.0 * (double)j.dw &&
@@ -386,8 +405,8 @@ static kr_status enqueue_batch(const kr_batch_item *items, int n, int c, kr_dtyp
         return st;
     if (n == 0)
         return KR_OK;
-    if (!tiled_supported(c, src_t))
-        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+    if (!tiled_image_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources");
     if (!table || reinterpret_cast<uintptr_t>(table) % 256 != 0)
         return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
     if (table_bytes < kr_resize_batch_workspace_size(n))
@@ -549,8 +568,8 @@ kr_status kr_batch_plan_create_ex(const kr_batch_item *items, int n, int c, kr_d
         return st;
     if (n == 0)
         return fail(KR_ERR_INVALID_ARGUMENT, "a plan needs at least one item");
-    if (!tiled_supported(c, src_t))
-        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+    if (!tiled_image_supported(c, src_t))
+        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources");
     if (dst_layout != KR_LAYOUT_HWC && dst_layout != KR_LAYOUT_CHW)
         return fail(KR_ERR_INVALID_ARGUMENT, "unknown destination layout %d", dst_layout);
     Epilogue e = make_epilogue(c, border, border_value, norm);
@@ -646,7 +665,7 @@ extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c,
     if (st != KR_OK)
         return st;
     if (!tiled_supported(c, src_t))
-        return fail(KR_ERR_UNSUPPORTED, "batched launches need u8 sources with 3 or 4 channels");
+        return fail(KR_ERR_UNSUPPORTED, "only batches of u8 sources with 3 or 4 channels have tunable configurations");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
     if (workspace_bytes < kr_resize_batch_workspace_size(n))

@@ -33,6 +33,8 @@ struct TileCfg {
 #define KR_RESIZE_CFGS_NARROW(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 64, 1, 1)
 #define KR_BATCH_WARP_CFGS(X) X(4, 16, 1, 1) X(4, 16, 1, 2) X(4, 8, 1, 1) X(1, 64, 1, 4) X(1, 64, 1, 8)
 #define KR_BATCH_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 64, 1, 1) X(1, 64, 1, 4) X(1, 64, 2, 4)
+#define KR_BATCH_WARP_CFGS_NARROW(X) X(4, 16, 1, 1)
+#define KR_BATCH_RESIZE_CFGS_NARROW(X) X(4, 16, 1, 1)
 
 // Launch one image with an explicit configuration; fits = false (nothing
 // launched) when its LDS footprint exceeds the per-workgroup budget.
@@ -47,11 +49,11 @@ TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th);
 TileGeom tile_geom(const ImageJob &j, int op, int tw, int th);
 size_t tile_lds_bytes(const TileGeom &G, int tw, int th);
 bool wants_gather(const ImageJob &j, int op);
-// u8 sources with 3 or 4 channels: every tiled path (images, batches, the
-// serving loop, the autotuner).
+// u8 sources with 3 or 4 channels: every tiled path, the serving loop and
+// the autotuner included.
 bool tiled_supported(int c, kr_dtype st);
-// u8 sources with 1-4 channels: the per-image tiled kernels (untuned
-// configurations for 1 and 2 channels).
+// u8 sources with 1-4 channels: the tiled kernels of single images and
+// batches (untuned configurations for 1 and 2 channels).
 bool tiled_image_supported(int c, kr_dtype st);
 
 }  // namespace kr

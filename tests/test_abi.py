@@ -175,7 +175,7 @@ def test_batch_validation():
         == kr.ERR_INVALID_ARGUMENT  # misaligned workspace
     assert L.kr_resize_batch(batch_items(op=7), 2, 3, 0, 0, 1, 0.0, None, ws, 1 << 20, None) \
         == kr.ERR_INVALID_ARGUMENT
-    assert L.kr_resize_batch(batch_items(), 2, 1, 0, 0, 1, 0.0, None, ws, 1 << 20, None) == kr.ERR_UNSUPPORTED
+    assert L.kr_resize_batch(batch_items(), 2, 5, 0, 0, 1, 0.0, None, ws, 1 << 20, None) == kr.ERR_UNSUPPORTED
     assert L.kr_resize_batch(batch_items(), 2, 3, 1, 1, 1, 0.0, None, ws, 1 << 20, None) == kr.ERR_UNSUPPORTED
     assert L.kr_resize_batch(None, 0, 3, 0, 0, 1, 0.0, None, None, 0, None) == kr.OK
     arr = batch_items(op=1)

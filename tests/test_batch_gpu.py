@@ -71,7 +71,7 @@ def test_batch_64_warps_1080p_u8():
         assert np.array_equal(single.cpu().numpy(), got), f"item {i}: batch != single"
 
 
-@pytest.mark.parametrize("c,out", [(3, "u8"), (3, "f32"), (4, "u8")])
+@pytest.mark.parametrize("c,out", [(3, "u8"), (3, "f32"), (4, "u8"), (1, "u8"), (2, "f32")])
 def test_mixed_batch_and_plan_replays(c, out):
     rng = np.random.default_rng(7 + c)
     dt = torch.uint8 if out == "u8" else torch.float32
@@ -223,7 +223,7 @@ def test_warp_batch_launch_box_budget(out):
                              f"item {i}")
 
 
-@pytest.mark.parametrize("c,out", [(3, "f32"), (3, "u8"), (4, "u8"), (4, "f32")])
+@pytest.mark.parametrize("c,out", [(3, "f32"), (3, "u8"), (4, "u8"), (4, "f32"), (1, "f32"), (2, "u8")])
 def test_planar_layout_equals_interleaved(c, out):
     """CHW destinations hold exactly the HWC results, transposed, for a mixed
     batch of resizes and warps (single launch and plan); spot-checked against

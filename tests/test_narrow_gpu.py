@@ -111,6 +111,45 @@ def test_narrow_perspective(c):
                 assert_f32_close(d.cpu().numpy(), exp, "narrow perspective f32")
 
 
+@pytest.mark.parametrize("c,out", [(1, "u8"), (2, "u8"), (1, "f32"), (2, "f32")])
+def test_narrow_batch_equals_single_calls(c, out):
+    """A mixed batch (resizes, exact halvings, warps, constant border) equals
+    the single-image calls on the same items bit for bit, and the oracle."""
+    rng = np.random.default_rng(500 + c)
+    dt = torch.uint8 if out == "u8" else torch.float32
+    specs, refs = [], []
+    for i in range(12):
+        h, w = int(rng.integers(30, 600)), int(rng.integers(30, 600))
+        im = wl.uniform_u8(h, w, c, seed=600 + 13 * i + c)
+        if i % 3 == 0:
+            dh, dw = int(rng.integers(16, 500)), int(rng.integers(16, 500))
+            m = wl.affine_compose(h, w, rng.uniform(-45, 45), rng.uniform(0.4, 1.8), rng.uniform(-0.2, 0.2),
+                                  (dw - w) / 2.0, (dh - h) / 2.0)
+            specs.append({"op": "warp", "src": dev(im), "m": m, "dst": torch.empty((dh, dw, c), dtype=dt, device="cuda")})
+            refs.append(oracle.warp(im, m, dh, dw, out if out == "u8" else "f64", False, CONST, 40, threads=TH))
+        else:
+            dh, dw = (h // 2, w // 2) if i % 3 == 1 else (int(rng.integers(8, 700)), int(rng.integers(8, 700)))
+            dh, dw = max(dh, 1), max(dw, 1)
+            specs.append({"op": "resize", "src": dev(im), "dst": torch.empty((dh, dw, c), dtype=dt, device="cuda")})
+            refs.append(oracle.resize(im, dh, dw, out if out == "u8" else "f64", CONST, 40, threads=TH))
+    say(f"narrow batch c={c} out={out}")
+    kr.resize_batch(specs, border=CONST, border_value=40.0)
+    torch.cuda.synchronize()
+    for i, (sp, ref) in enumerate(zip(specs, refs)):
+        d = torch.empty_like(sp["dst"])
+        if sp["op"] == "warp":
+            kr.warp_affine(sp["src"], d, sp["m"], border=CONST, border_value=40.0)
+        else:
+            kr.resize(sp["src"], d, border=CONST, border_value=40.0)
+        torch.cuda.synchronize()
+        got = sp["dst"].cpu().numpy()
+        assert np.array_equal(got.view(np.uint8), d.cpu().numpy().view(np.uint8)), f"item {i}: batch != single"
+        if out == "u8":
+            assert_u8_equal(got, ref, f"narrow batch item {i}")
+        else:
+            assert_f32_close(got, ref, f"narrow batch item {i}")
+
+
 def test_narrow_4k_warp():
     img = wl.mixed_u8(2160, 3840, 1, seed=0)
     check_warp(img, wl.random_affine_4k(2160, 3840, 0), 2160, 3840, CONST, 0, what="4K gray seed 0")
