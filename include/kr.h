@@ -352,7 +352,7 @@ kr_status kr_invert_affine(const double m[6], double inv[6]);
  * owned device images that must stay valid until their request completes.
  * A server is driven by one host thread at a time (calls on one server must
  * not overlap); different servers are independent.  Supported: u8 sources
- * with 3 or 4 channels, u8 or f32 outputs.
+ * with 1-4 channels, u8 or f32 outputs.
  */
 typedef struct kr_server kr_server;
 

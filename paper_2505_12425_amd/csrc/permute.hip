@@ -131,14 +131,9 @@ __global__ __launch_bounds__(PM_THREADS) void k_permute(PermJob pj, Epilogue ep)
     const uint8_t *src = static_cast<const uint8_t *>(j.src);
     const int lo = j.sk, hi = src_end(j);
     const int nrows = yb - ya + 1;
-    bool staged = false;
-    if constexpr (C >= 3) {
-        if (xa >= 0 && xb < j.sw && ya >= 0 && yb < j.sh) {
-            stage_groups<C>(blk, src, lo, hi, j.sp, xa, xb, ya, nrows);
-            staged = true;
-        }
-    }
-    if (!staged)
+    if (xa >= 0 && xb < j.sw && ya >= 0 && yb < j.sh)
+        stage_groups<C>(blk, src, lo, hi, j.sp, xa, xb, ya, nrows);
+    else
         stage_pixels<C>(blk, j, ep, xa, xb, ya, nrows);
     __syncthreads();
     // destination: TW / 4 lanes of 4 pixels per row

@@ -173,8 +173,8 @@ kr_status kr_server_create(const kr_server_config *cfg, int c, kr_dtype src_t, k
                                              "1 <= max_batch <= 4096)");
     if (c < 1 || c > 4)
         return fail(KR_ERR_UNSUPPORTED, "channel count %d not in [1, 4]", c);
-    if (!tiled_supported(c, src_t) || !(dst_t == KR_U8 || dst_t == KR_F32))
-        return fail(KR_ERR_UNSUPPORTED, "the server needs u8 sources with 3 or 4 channels");
+    if (!tiled_image_supported(c, src_t) || !(dst_t == KR_U8 || dst_t == KR_F32))
+        return fail(KR_ERR_UNSUPPORTED, "the server needs u8 sources");
     if (border != KR_BORDER_CONSTANT && border != KR_BORDER_REPLICATE)
         return fail(KR_ERR_UNSUPPORTED, "border mode %d not supported", (int)border);
     if (!std::isfinite(border_value) || border_value < 0.0f || border_value > 255.0f ||

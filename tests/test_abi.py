@@ -204,7 +204,7 @@ def test_server_config_validation():
         assert L.kr_server_create(ctypes.byref(cfg), 3, kr.U8, kr.U8, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
             == kr.ERR_INVALID_ARGUMENT
     ok = kr.ServerConfig(1 << 20, 2, 8)
-    assert L.kr_server_create(ctypes.byref(ok), 1, kr.U8, kr.U8, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
+    assert L.kr_server_create(ctypes.byref(ok), 5, kr.U8, kr.U8, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
         == kr.ERR_UNSUPPORTED
     assert L.kr_server_create(ctypes.byref(ok), 3, kr.F32, kr.F32, kr.REPLICATE, 0.0, None, ctypes.byref(h)) \
         == kr.ERR_UNSUPPORTED

@@ -64,7 +64,7 @@ def _serve(reqs, srcs, c, out, budget, slots, max_batch):
     return results
 
 
-@pytest.mark.parametrize("c,out", [(3, "u8"), (3, "f32"), (4, "u8")])
+@pytest.mark.parametrize("c,out", [(3, "u8"), (3, "f32"), (4, "u8"), (1, "u8"), (2, "f32")])
 def test_served_alone_equals_served_in_mix(c, out):
     rng = np.random.default_rng(11 + c)
     reqs = _requests(rng, 30, c)
