@@ -36,7 +36,7 @@ kr_status kr_autotune_image(int op, const void *src, int src_h, int src_w, int c
     kr_status st = check_common(src, src_h, src_w, c, src_t, dst, dst_h, dst_w, dst_t, border, border_value, norm);
     if (st != KR_OK)
         return st;
-    if (!tiled_supported(c, src_t))
+    if (!tunable_source(c, src_t))
         return fail(KR_ERR_UNSUPPORTED, "only u8 sources with 3 or 4 channels have tunable configurations");
     if (reps < 1 || reps > 1000)
         return fail(KR_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");

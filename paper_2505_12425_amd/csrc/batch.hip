@@ -664,7 +664,7 @@ extern "C" kr_status kr_autotune_batch(const kr_batch_item *items, int n, int c,
     kr_status st = check_items(items, n, c, src_t, dst_t, border, border_value, norm, imgs[0], imgs[1]);
     if (st != KR_OK)
         return st;
-    if (!tiled_supported(c, src_t))
+    if (!tunable_source(c, src_t))
         return fail(KR_ERR_UNSUPPORTED, "only batches of u8 sources with 3 or 4 channels have tunable configurations");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KR_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");

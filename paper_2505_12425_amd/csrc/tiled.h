@@ -1,6 +1,6 @@
-// tiled.h -- LDS-tiled bilinear resize and affine warp for u8 sources with
-// 3 or 4 interleaved channels (device code shared by the per-image and the
-// batched kernels).
+// tiled.h -- LDS-tiled bilinear resize, affine and perspective warp for u8
+// sources with 1-4 interleaved channels (device code shared by the per-image
+// and the batched kernels).
 //
 // One workgroup (4 waves) produces an output tile; each lane owns runs of PX
 // consecutive pixels (the lane layout is a template parameter, see Layout).

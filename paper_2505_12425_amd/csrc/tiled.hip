@@ -424,7 +424,7 @@ hipError_t launch_tiled_cfg(int op, int c, kr_dtype dt, const TileCfg &cfg, cons
              : launch_shape<OP_RESIZE, 4, false>(cfg, j, e, s, false, fits);
 }
 
-bool tiled_supported(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 4); }
+bool tunable_source(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 4); }
 
 bool tiled_image_supported(int c, kr_dtype st) { return st == KR_U8 && c >= 1 && c <= 4; }
 

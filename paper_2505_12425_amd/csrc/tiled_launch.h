@@ -49,11 +49,10 @@ TiledJob make_tiled_job(const ImageJob &j, int op, int tw, int th);
 TileGeom tile_geom(const ImageJob &j, int op, int tw, int th);
 size_t tile_lds_bytes(const TileGeom &G, int tw, int th);
 bool wants_gather(const ImageJob &j, int op);
-// u8 sources with 3 or 4 channels: every tiled path, the serving loop and
-// the autotuner included.
-bool tiled_supported(int c, kr_dtype st);
-// u8 sources with 1-4 channels: the tiled kernels of single images and
-// batches (untuned configurations for 1 and 2 channels).
+// u8 sources with 3 or 4 channels: the ones the autotuner takes.
+bool tunable_source(int c, kr_dtype st);
+// u8 sources with 1-4 channels: the tiled kernels of single images, batches
+// and the serving loop (fixed configurations for 1 and 2 channels).
 bool tiled_image_supported(int c, kr_dtype st);
 
 }  // namespace kr

@@ -1,7 +1,7 @@
 """GPU parity of the bilinear perspective warp (kr_warp_perspective) against
 the oracle, element by element: u8 bit-exact, f32 within 1e-3 on the 0..255
-scale.  Covers the LDS-tiled path (u8 sources, 3 or 4 channels), the
-per-pixel path (other channel counts, f32 sources), tiles whose corners reach
+scale.  Covers the LDS-tiled path (u8 sources), the per-pixel path (f32
+sources), tiles whose corners reach
 w <= 0 (horizon crossings: quotients of either sign, infinities and 0/0),
 both borders, the inverse flag, and the affine special case."""
 from __future__ import annotations
