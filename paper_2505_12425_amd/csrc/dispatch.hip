@@ -1,12 +1,14 @@
 // dispatch.hip -- chooses the kernel for one image: the exact-2x downscale
-// kernel where it applies, the LDS-tiled kernels for u8 sources, the
-// per-pixel kernels for f32 sources.
+// kernel where it applies, the LDS-tiled kernels for u8 sources and
+// one-channel f32 sources, the per-pixel kernels for other f32 sources.
 #include "kr_device.h"
 
 namespace kr {
 
 bool tiled_image_supported(int c, kr_dtype st);
+bool tiled_f32_supported(int c, kr_dtype st);
 hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s);
+hipError_t launch_tiled_f32(int op, const ImageJob &j, const Epilogue &e, hipStream_t s);
 
 hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
@@ -14,6 +16,8 @@ hipError_t launch_resize(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, con
         return launch_half(c, dt, j, e, s);
     if (tiled_image_supported(c, st))
         return launch_tiled(OP_RESIZE, c, dt, j, e, s);
+    if (tiled_f32_supported(c, st))
+        return launch_tiled_f32(OP_RESIZE, j, e, s);
     return launch_generic(OP_RESIZE, c, st, dt, j, e, s);
 }
 
@@ -33,6 +37,8 @@ hipError_t launch_warp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, const
         return launch_permute(c, dt, j, m, e, s);
     if (tiled_image_supported(c, st))
         return launch_tiled(OP_WARP, c, dt, j, e, s);
+    if (tiled_f32_supported(c, st))
+        return launch_tiled_f32(OP_WARP, j, e, s);
     return launch_generic(OP_WARP, c, st, dt, j, e, s);
 }
 
@@ -40,6 +46,8 @@ hipError_t launch_persp(int c, kr_dtype st, kr_dtype dt, const ImageJob &j, cons
 {
     if (tiled_image_supported(c, st))
         return launch_tiled(OP_PERSP, c, dt, j, e, s);
+    if (tiled_f32_supported(c, st))
+        return launch_tiled_f32(OP_PERSP, j, e, s);
     return launch_generic(OP_PERSP, c, st, dt, j, e, s);
 }
 

@@ -170,8 +170,11 @@ __device__ __forceinline__ uint32_t mask_weights(int x0, int y0, int W, int H, u
 // f32 interpolation with unquantised weights (blend4), plus the border's
 // share when EXTRA (CONSTANT border with masked taps), then
 // out = v * alpha + beta.  The operation order is fixed (explicit fma, no
-// contraction), so every kernel path produces the same bits.
-template <int C, bool EXTRA>
+// contraction), so every kernel path produces the same bits.  SF: the taps
+// are binary32 pixels of a one-channel f32 source; with EXTRA a tap whose
+// weight is zero counts as 0 (a masked tap's LDS word is not a pixel and may
+// hold any bits, a NaN included).
+template <int C, bool EXTRA, bool SF = false>
 __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t t10, uint32_t t11, float wx0,
                                            float wx1, float wy0, float wy1, float extra, const Epilogue &e,
                                            float (&o)[C])
@@ -179,10 +182,24 @@ __device__ __forceinline__ void interp_f32(uint32_t t00, uint32_t t01, uint32_t 
     const Weights2 w = weights2(wx0, wx1, wy0, wy1);
 #pragma unroll
     for (int c = 0; c < C; c++) {
-        const float p00 = (float)((t00 >> (8 * c)) & 0xFFu);
-        const float p01 = (float)((t01 >> (8 * c)) & 0xFFu);
-        const float p10 = (float)((t10 >> (8 * c)) & 0xFFu);
-        const float p11 = (float)((t11 >> (8 * c)) & 0xFFu);
+        float p00, p01, p10, p11;
+        if constexpr (SF) {
+            p00 = __builtin_bit_cast(float, t00);
+            p01 = __builtin_bit_cast(float, t01);
+            p10 = __builtin_bit_cast(float, t10);
+            p11 = __builtin_bit_cast(float, t11);
+            if constexpr (EXTRA) {
+                p00 = wx0 != 0.0f && wy0 != 0.0f ? p00 : 0.0f;
+                p01 = wx1 != 0.0f && wy0 != 0.0f ? p01 : 0.0f;
+                p10 = wx0 != 0.0f && wy1 != 0.0f ? p10 : 0.0f;
+                p11 = wx1 != 0.0f && wy1 != 0.0f ? p11 : 0.0f;
+            }
+        } else {
+            p00 = (float)((t00 >> (8 * c)) & 0xFFu);
+            p01 = (float)((t01 >> (8 * c)) & 0xFFu);
+            p10 = (float)((t10 >> (8 * c)) & 0xFFu);
+            p11 = (float)((t11 >> (8 * c)) & 0xFFu);
+        }
         float v = blend4(p00, p01, p10, p11, w);
         if constexpr (EXTRA)
             v = v + extra;
@@ -1029,7 +1046,7 @@ __device__ __forceinline__ bool layout_aligned(int dw)
 
 // PERSP: perspective warp (coordinates by persp_coord, always clamped; m is
 // then the unscaled inverse map and the u8 path scales the quotients).
-template <int C, bool F32, class L, bool CLAMP, bool MASK, bool PERSP>
+template <int C, bool F32, class L, bool CLAMP, bool MASK, bool PERSP, bool SF = false>
 __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                                const uint32_t *lds)
 {
@@ -1161,8 +1178,8 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
                         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
                     }
                     const int a = __mul24(y0, pitch) + x0 - base;
-                    interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
-                                        extra, ev, o[k]);
+                    interp_f32<C, MASK, SF>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0,
+                                            wy1, extra, ev, o[k]);
                 }
                 store_row_f32<C, PX, L::NT>(j, e, y, xr, x_end, aligned, o);
             }
@@ -1170,19 +1187,19 @@ __device__ __forceinline__ void compute_warp_t(const TiledJob &t, const Plan &p,
     }
 }
 
-template <int C, bool F32, class L, bool PERSP>
+template <int C, bool F32, class L, bool PERSP, bool SF = false>
 __device__ __forceinline__ void compute_warp(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                              const uint32_t *lds)
 {
     if (p.inside)
-        compute_warp_t<C, F32, L, false, false, PERSP>(t, p, G, e, lds);
+        compute_warp_t<C, F32, L, false, false, PERSP, SF>(t, p, G, e, lds);
     else if (e.border == KR_BORDER_CONSTANT)
-        compute_warp_t<C, F32, L, true, true, PERSP>(t, p, G, e, lds);
+        compute_warp_t<C, F32, L, true, true, PERSP, SF>(t, p, G, e, lds);
     else
-        compute_warp_t<C, F32, L, true, false, PERSP>(t, p, G, e, lds);
+        compute_warp_t<C, F32, L, true, false, PERSP, SF>(t, p, G, e, lds);
 }
 
-template <int C, bool F32, class L, bool MASK>
+template <int C, bool F32, class L, bool MASK, bool SF = false>
 __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                                  const uint32_t *lds)
 {
@@ -1254,8 +1271,8 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
                         wy1 = vy1 ? wy1 : 0.0f;
                         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
                     }
-                    interp_f32<C, MASK>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0, wy1,
-                                        extra, ev, o[k]);
+                    interp_f32<C, MASK, SF>(lds[a], lds[a + 1], lds[a + pitch], lds[a + pitch + 1], wx0, wx1, wy0,
+                                            wy1, extra, ev, o[k]);
                 }
                 store_row_f32<C, PX, L::NT>(j, e, y, xr, x_end, aligned, o);
             }
@@ -1263,14 +1280,14 @@ __device__ __forceinline__ void compute_resize_t(const TiledJob &t, const Plan &
     }
 }
 
-template <int C, bool F32, class L>
+template <int C, bool F32, class L, bool SF = false>
 __device__ __forceinline__ void compute_resize(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                                const uint32_t *lds)
 {
     if (!p.inside && e.border == KR_BORDER_CONSTANT)
-        compute_resize_t<C, F32, L, true>(t, p, G, e, lds);
+        compute_resize_t<C, F32, L, true, SF>(t, p, G, e, lds);
     else
-        compute_resize_t<C, F32, L, false>(t, p, G, e, lds);
+        compute_resize_t<C, F32, L, false, SF>(t, p, G, e, lds);
 }
 
 // ------------------------------------------------------------------ gather path
@@ -1358,12 +1375,13 @@ __device__ __forceinline__ uint32_t gather_px_u8(const ImageJob &j, const Epilog
     return pack_px<C>(v);
 }
 
-template <int C>
+// SF: one-channel f32 source (taps read as 4-byte pixels).
+template <int C, bool SF = false>
 __device__ __forceinline__ void gather_px_f32(const ImageJob &j, const Epilogue &e, int x0, int y0, float fx, float fy,
                                               float (&o)[C])
 {
     uint32_t t00, t01, t10, t11;
-    const bool in = load_taps<C>(j, x0, y0, t00, t01, t10, t11);
+    const bool in = load_taps<SF ? 4 : C>(j, x0, y0, t00, t01, t10, t11);
     float wx0 = 1.0f - fx, wx1 = fx, wy0 = 1.0f - fy, wy1 = fy, extra = 0.0f;
     if (!in && e.border == KR_BORDER_CONSTANT) {
         const int W = j.sw, H = j.sh;
@@ -1373,10 +1391,10 @@ __device__ __forceinline__ void gather_px_f32(const ImageJob &j, const Epilogue 
         wy1 = (unsigned)(y0 + 1) < (unsigned)H ? wy1 : 0.0f;
         extra = e.bval_f * (1.0f - (wy0 + wy1) * (wx0 + wx1));
     }
-    interp_f32<C, true>(t00, t01, t10, t11, wx0, wx1, wy0, wy1, extra, e, o);
+    interp_f32<C, true, SF>(t00, t01, t10, t11, wx0, wx1, wy0, wy1, extra, e, o);
 }
 
-template <int OP, int C, bool F32, class L>
+template <int OP, int C, bool F32, class L, bool SF = false>
 __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p, const TileGeom &G, const Epilogue &e,
                                                const uint32_t *lds)
 {
@@ -1462,7 +1480,7 @@ __device__ __forceinline__ void compute_gather(const TiledJob &t, const Plan &p,
                 if constexpr (!F32)
                     P[k] = gather_px_u8<C>(j, e, x0, y0, wx1, wy1);
                 else
-                    gather_px_f32<C>(j, e, x0, y0, fx, fy, o[k]);
+                    gather_px_f32<C, SF>(j, e, x0, y0, fx, fy, o[k]);
             }
             if constexpr (!F32)
                 store_row_u8<C, PX>(j, e, y, xr, x_end, aligned, P, sel);
@@ -1514,9 +1532,13 @@ __device__ __forceinline__ void fill_blank(const TiledJob &t, const Plan &p, con
 // The next tile's global loads stay in flight in registers while this tile is
 // interpolated from LDS.  PIPE = false: the workgroup owns exactly one tile
 // (no registers stay reserved for a next tile during the interpolation).
-template <int OP, int C, bool F32, class L, int MAXIT, bool PIPE, typename NextJob>
+// SF: a one-channel f32 source (C = 1, f32 output): its 4-byte pixels are
+// staged as the 4-byte pixels of RGBA u8 are, one LDS word per pixel.
+template <int OP, int C, bool F32, class L, int MAXIT, bool PIPE, bool SF = false, typename NextJob>
 __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, uint32_t *lds, NextJob next_job)
 {
+    static_assert(!SF || (C == 1 && F32), "f32 sources: one channel, f32 output");
+    constexpr int SB = SF ? 4 : C;  // source bytes per pixel
     constexpr int TW = L::TW;
     constexpr int TH = L::TH;
     TiledJob t;
@@ -1527,37 +1549,37 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
     Plan p = make_plan<OP, TW, TH, F32>(t, tile, G, cb);
     if constexpr (!PIPE) {
         if (!p.direct) {
-            Prefetch<C, MAXIT> pf;
-            prefetch_urgent<OP, C, MAXIT>(t, p, G, pf);
-            commit<OP, C, MAXIT>(t, p, G, pf, lds, threadIdx.x);
+            Prefetch<SB, MAXIT> pf;
+            prefetch_urgent<OP, SB, MAXIT>(t, p, G, pf);
+            commit<OP, SB, MAXIT>(t, p, G, pf, lds, threadIdx.x);
         }
         if constexpr (OP == OP_RESIZE)
             resize_tables<TW, TH, F32>(t, p, G, lds, threadIdx.x);
         __syncthreads();
         if (needs_edge_fill(t, p, e)) {
-            fill_edge_columns<OP, C>(t, p, G, lds, threadIdx.x);
+            fill_edge_columns<OP, SB>(t, p, G, lds, threadIdx.x);
             __syncthreads();
         }
         if (p.blank)
             fill_blank<C, F32, L>(t, p, e);
         else if (p.direct)
-            compute_gather<OP, C, F32, L>(t, p, G, e, lds);
+            compute_gather<OP, C, F32, L, SF>(t, p, G, e, lds);
         else if constexpr (OP == OP_RESIZE)
-            compute_resize<C, F32, L>(t, p, G, e, lds);
+            compute_resize<C, F32, L, SF>(t, p, G, e, lds);
         else
-            compute_warp<C, F32, L, OP == OP_PERSP>(t, p, G, e, lds);
+            compute_warp<C, F32, L, OP == OP_PERSP, SF>(t, p, G, e, lds);
         return;
     }
-    Prefetch<C, MAXIT> pf;
-    prefetch_urgent<OP, C, MAXIT>(t, p, G, pf);
+    Prefetch<SB, MAXIT> pf;
+    prefetch_urgent<OP, SB, MAXIT>(t, p, G, pf);
     while (true) {
         if (!p.direct)
-            commit<OP, C, MAXIT>(t, p, G, pf, lds, threadIdx.x);
+            commit<OP, SB, MAXIT>(t, p, G, pf, lds, threadIdx.x);
         if constexpr (OP == OP_RESIZE)
             resize_tables<TW, TH, F32>(t, p, G, lds, threadIdx.x);
         __syncthreads();
         if (needs_edge_fill(t, p, e)) {
-            fill_edge_columns<OP, C>(t, p, G, lds, threadIdx.x);
+            fill_edge_columns<OP, SB>(t, p, G, lds, threadIdx.x);
             __syncthreads();
         }
         TiledJob nt;
@@ -1566,16 +1588,16 @@ __device__ __forceinline__ void run_tiles(const TileGeom &G, const Epilogue &e, 
         Plan np;
         if (more) {
             np = make_plan<OP, TW, TH, F32>(nt, ntile, G, cb);
-            prefetch_urgent<OP, C, MAXIT>(nt, np, G, pf);
+            prefetch_urgent<OP, SB, MAXIT>(nt, np, G, pf);
         }
         if (p.blank)
             fill_blank<C, F32, L>(t, p, e);
         else if (p.direct)
-            compute_gather<OP, C, F32, L>(t, p, G, e, lds);
+            compute_gather<OP, C, F32, L, SF>(t, p, G, e, lds);
         else if constexpr (OP == OP_RESIZE)
-            compute_resize<C, F32, L>(t, p, G, e, lds);
+            compute_resize<C, F32, L, SF>(t, p, G, e, lds);
         else
-            compute_warp<C, F32, L, OP == OP_PERSP>(t, p, G, e, lds);
+            compute_warp<C, F32, L, OP == OP_PERSP, SF>(t, p, G, e, lds);
         if (!more)
             break;
         __syncthreads();

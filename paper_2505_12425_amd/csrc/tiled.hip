@@ -25,7 +25,9 @@ __global__ __launch_bounds__(KT_THREADS) void k_tiled(TiledJob job, Epilogue e, 
     TileSeq seq(blockIdx.x, gridDim.x, job.ntiles);
     // f32 outputs leave through non-temporal stores (no kernel of the call
     // reads them back)
-    run_tiles<OP, C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, PERS>(G, e, lds, [&](TiledJob &t, int &tile) {
+    constexpr bool SF = C == KT_F32_SOURCE;
+    run_tiles<OP, SF ? 1 : C, F32, Layout<PX, TXT, CPT, RPT, true>, MAXIT, PERS, SF>(G, e, lds,
+                                                                                     [&](TiledJob &t, int &tile) {
         if (!seq.take(tile))
             return false;
         t = job;
@@ -289,7 +291,7 @@ static hipError_t launch_cfg(const ImageJob &j, const Epilogue &e, hipStream_t s
     fits = lds <= KT_LDS_CAP;
     if (!fits)
         return hipSuccess;
-    if constexpr (C >= 3) {  // one- and two-channel sources: one workgroup per tile
+    if constexpr (C == 3 || C == 4) {  // other sources: one workgroup per tile
         if (mode == GRID_PERSISTENT) {
             auto kern = k_tiled<OP, C, F32, PX, TXT, CPT, RPT, MAXIT_PERS, true>;
             const int grid = persistent_grid(t.ntiles, blocks_per_cu(reinterpret_cast<const void *>(kern), lds));
@@ -309,7 +311,7 @@ static hipError_t launch_shape(const TileCfg &cfg, const ImageJob &j, const Epil
 #define KR_TRY(PX, TXT, CPT, RPT)                                                                        \
     if (cfg.px == PX && cfg.txt == TXT && cfg.cpt == CPT && cfg.rpt == RPT)                              \
         return launch_cfg<OP, C, F32, PX, TXT, CPT, RPT>(j, e, s, cfg.grid, gather, fits);
-    if constexpr (C < 3) {
+    if constexpr (C < 3 || C == KT_F32_SOURCE) {
         if constexpr (OP != OP_RESIZE) {
             KR_WARP_CFGS_NARROW(KR_TRY)
         } else {
@@ -387,7 +389,7 @@ static hipError_t launch_c(const ImageJob &j, const Epilogue &e, hipStream_t s)
     TileCfg tuned;
     if (tune_lookup(tune_key_image(OP, C, F32, j), &tuned))
         cfgs[n++] = tuned;
-    n += default_cfgs(OP, F32, wants_gather(j, OP), C < 3, cfgs + n);
+    n += default_cfgs(OP, F32, wants_gather(j, OP), C < 3 || C == KT_F32_SOURCE, cfgs + n);
     for (int i = 0; i < n; i++) {
         bool fits = false;
         const hipError_t err = launch_shape<OP, C, F32>(cfgs[i], j, e, s, false, fits);
@@ -428,6 +430,8 @@ bool tunable_source(int c, kr_dtype st) { return st == KR_U8 && (c == 3 || c == 
 
 bool tiled_image_supported(int c, kr_dtype st) { return st == KR_U8 && c >= 1 && c <= 4; }
 
+bool tiled_f32_supported(int c, kr_dtype st) { return st == KR_F32 && c == 1; }
+
 template <int OP>
 static hipError_t launch_op(int c, bool f, const ImageJob &j, const Epilogue &e, hipStream_t s)
 {
@@ -441,6 +445,15 @@ static hipError_t launch_op(int c, bool f, const ImageJob &j, const Epilogue &e,
     default:
         return f ? launch_c<OP, 4, true>(j, e, s) : launch_c<OP, 4, false>(j, e, s);
     }
+}
+
+hipError_t launch_tiled_f32(int op, const ImageJob &j, const Epilogue &e, hipStream_t s)
+{
+    if (op == OP_PERSP)
+        return launch_c<OP_PERSP, KT_F32_SOURCE, true>(j, e, s);
+    if (op == OP_WARP)
+        return launch_c<OP_WARP, KT_F32_SOURCE, true>(j, e, s);
+    return launch_c<OP_RESIZE, KT_F32_SOURCE, true>(j, e, s);
 }
 
 hipError_t launch_tiled(int op, int c, kr_dtype dt, const ImageJob &j, const Epilogue &e, hipStream_t s)

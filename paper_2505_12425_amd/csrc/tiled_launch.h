@@ -28,6 +28,10 @@ struct TileCfg {
 #define KR_WARP_CFGS(X) X(4, 16, 1, 2) X(4, 16, 1, 4) X(4, 8, 1, 1) X(1, 64, 1, 8) X(1, 64, 1, 16)
 #define KR_RESIZE_CFGS(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 32, 1, 2) X(4, 64, 1, 1) X(4, 64, 1, 2) \
     X(1, 64, 2, 4) X(1, 64, 4, 2)
+// Channel code of the tiled kernels for a one-channel f32 source (f32
+// output): its pixels are staged as 4-byte words, as RGBA u8 pixels are.
+constexpr int KT_F32_SOURCE = 5;
+
 // One- and two-channel sources: 4-pixel runs only.
 #define KR_WARP_CFGS_NARROW(X) X(4, 16, 1, 2) X(4, 16, 1, 4) X(4, 8, 1, 1)
 #define KR_RESIZE_CFGS_NARROW(X) X(4, 16, 1, 1) X(4, 32, 1, 1) X(4, 64, 1, 1)
@@ -54,5 +58,7 @@ bool tunable_source(int c, kr_dtype st);
 // u8 sources with 1-4 channels: the tiled kernels of single images, batches
 // and the serving loop (fixed configurations for 1 and 2 channels).
 bool tiled_image_supported(int c, kr_dtype st);
+// One-channel f32 sources (f32 output): single images on the tiled kernels.
+bool tiled_f32_supported(int c, kr_dtype st);
 
 }  // namespace kr

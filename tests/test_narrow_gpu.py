@@ -1,10 +1,10 @@
-"""GPU parity of one- and two-channel u8 sources, which run on the LDS-tiled
-kernels (one workgroup per tile, runs of 4 pixels per lane): warps over the
-shapes of the RGB parity cases (rotations, shrinks, zooms, tiles that are all
-border), resizes that stage boxes or gather their taps from global memory,
-perspective warps, views into larger buffers, normalised outputs and a 4K
-warp, each against the oracle (u8 bit-exact, f32 within 1e-3 absolute on the
-0..255 scale)."""
+"""GPU parity of one- and two-channel u8 sources and one-channel f32 sources,
+which run on the LDS-tiled kernels (one workgroup per tile, runs of 4 pixels
+per lane): warps over the shapes of the RGB parity cases (rotations, shrinks,
+zooms, tiles that are all border), resizes that stage boxes or gather their
+taps from global memory, perspective warps, views into larger buffers,
+normalised outputs, batches and 4K warps, each against the oracle (u8
+bit-exact, f32 within 1e-3 absolute on the 0..255 scale)."""
 from __future__ import annotations
 
 import numpy as np
@@ -150,6 +150,54 @@ def test_narrow_batch_equals_single_calls(c, out):
             assert_f32_close(got, ref, f"narrow batch item {i}")
 
 
+# ------------------------------------------------------------------ one-channel f32 sources
+@pytest.mark.parametrize("k", range(len(WARPS)))
+@pytest.mark.parametrize("border,bval", [(CONST, -3.5), (REPL, 0)])
+def test_f32_gray_source_warps(k, border, bval):
+    """One-channel f32 sources (depth-map-like values) stage their 4-byte
+    pixels in LDS; edge tiles with a constant border must ignore the LDS
+    words of masked taps."""
+    h, w, dh, dw, th, s, sh, tx, ty = WARPS[k]
+    img = wl.uniform_f32(h, w, 1, seed=200 + k)
+    m = wl.affine_compose(h, w, th, s, sh, tx, ty)
+    check_warp(img, m, dh, dw, border, bval, what=f"f32 gray case {k}")
+
+
+@pytest.mark.parametrize("shape", [(123, 77, 250, 160), (1080, 1920, 700, 1000), (300, 410, 47, 1201),
+                                   (2160, 240, 224, 224), (31, 1, 7, 45), (64, 48, 32, 24)])
+@pytest.mark.parametrize("border,bval", [(CONST, 7.25), (REPL, 0)])
+def test_f32_gray_source_resizes(shape, border, bval):
+    h, w, dh, dw = shape
+    img = wl.uniform_f32(h, w, 1, seed=h + 3 * w)
+    check_resize(img, dh, dw, border, bval, what="f32 gray")
+
+
+def test_f32_gray_source_perspective_views_norm():
+    img = wl.uniform_f32(240, 320, 1, seed=77)
+    m9 = np.array([[0.9, 0.08, 12.0], [-0.05, 1.1, 4.0], [2e-4, -1e-4, 1.0]])
+    for border, bval in ((CONST, 99.0), (REPL, 0.0)):
+        say(f"f32 gray perspective border={border}")
+        d = torch.empty((250, 300, 1), dtype=torch.float32, device="cuda")
+        kr.warp_perspective(dev(img), d, m9, border=border, border_value=bval)
+        torch.cuda.synchronize()
+        assert_f32_close(d.cpu().numpy(), oracle.warp_perspective(img, m9, 250, 300, "f64", False, border, bval,
+                                                                   threads=TH), "f32 gray perspective")
+    par = wl.uniform_f32(260, 700, 1, seed=78)
+    dev_par = dev(par)
+    m = wl.affine_compose(100, 200, 12.0, 1.05, 0.0, 2.0, 1.0)
+    for (y, x, h, w) in ((1, 3, 100, 200), (0, 0, 260, 700), (160, 500, 100, 200), (7, 13, 33, 41)):
+        say(f"f32 gray view {y},{x},{h}x{w}")
+        view = dev_par[y:y + h, x:x + w]
+        host = np.ascontiguousarray(par[y:y + h, x:x + w])
+        d = torch.empty((90, 170, 1), dtype=torch.float32, device="cuda")
+        kr.warp_affine(view, d, m, border=CONST, border_value=1.5, mean=(0.3,), std=(0.2,))
+        torch.cuda.synchronize()
+        assert_f32_close(d.cpu().numpy(), oracle.warp(host, m, 90, 170, "f64", False, CONST, 1.5, (0.3,), (0.2,),
+                                                      threads=TH), "f32 gray view norm", std=(0.2,))
+
+
 def test_narrow_4k_warp():
     img = wl.mixed_u8(2160, 3840, 1, seed=0)
     check_warp(img, wl.random_affine_4k(2160, 3840, 0), 2160, 3840, CONST, 0, what="4K gray seed 0")
+    check_warp(wl.uniform_f32(2160, 3840, 1, seed=1), wl.random_affine_4k(2160, 3840, 3), 2160, 3840, CONST, 2.0,
+               what="4K f32 gray seed 3")
