@@ -56,7 +56,8 @@ def label(name: str) -> str:
         kind, op, c, f32, px, txt, cpt, rpt = m.groups()
         dt = "f32" if f32 == "true" else "u8"
         pre = "batch_" if kind == "batch" else ""
-        return f"{pre}{_OPS[op]}_{dt} c{c} {px}x{txt}x{cpt}x{rpt}"
+        src = " c1 f32-source" if c == "5" else f" c{c}"  # channel code 5: one-channel f32 source
+        return f"{pre}{_OPS[op]}_{dt}{src} {px}x{txt}x{cpt}x{rpt}"
     if "k_copy" in name:
         return "copy"
     if "k_stream" in name:

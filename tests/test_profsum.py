@@ -33,6 +33,8 @@ def test_labels_and_keys():
     tiled_r = "void kr::k_tiled<0, 3, false, 4, 16, 1, 1, 3, false>(kr::TiledJob, kr::Epilogue, kr::TileGeom)"
     assert profsum.bench_key(tiled_r) == "resize_tiled_u8" and profsum.label(tiled_r) == "resize_u8 c3 4x16x1x1"
     assert profsum.bench_key("void kr::k_batch<0, 3, true, 1, 64, 1, 4, 3, false>(x)") == "batch_resize_f32"
+    f32src = "void kr::k_tiled<1, 5, true, 4, 16, 1, 2, 3, false>(kr::TiledJob, kr::Epilogue, kr::TileGeom)"
+    assert profsum.label(f32src) == "warp_f32 c1 f32-source 4x16x1x2" and profsum.bench_key(f32src) is None
     assert profsum.bench_key(TILED_W.replace("<1, 3,", "<1, 4,")) is None  # only 3-channel kernels are benchmarked
 
 
