@@ -27,7 +27,9 @@ per-image launches), --workload serve (continuous-batching request stream;
 p50/p99 latency), --workload ops (nearest-neighbour resize 4K <-> 1080p,
 flip, RGB -> gray, perspective warp, a quarter turn and the fused
 resample + gray forms at 4K), --workload warpseeds (the 4K
-warp for seeds 0-4 of its map).
+warp for seeds 0-4 of its map), --workload channels (the 4K warp and a
+4K -> 1440p resize of one- and two-channel u8 sources and of f32 sources,
+and quarter turns and flips of one- and two-channel u8 sources).
 
 Prints ONE JSON line.  Kernel durations come from HIP events recorded around
 every launch on the launch stream; the roofline entry uses the kernel with the
@@ -729,6 +731,86 @@ def bench_ops(args, torch, kr, wl):
     }
 
 
+def bench_channels(args, torch, kr, wl):
+    """Sources other than RGB u8: one- and two-channel u8 and one-channel f32
+    sources (the LDS-tiled kernels), RGB f32 sources (the per-pixel kernel),
+    through the seed-0 4K warp and a 4K -> 2560x1440 resize; quarter turns and
+    flips (the permutation kernel) of one- and two-channel u8 sources.
+    Per-launch duration with destinations rotating and cold sources."""
+    copies = args.cold_copies
+    h, w = 2160, 3840
+    m = wl.random_affine_4k(h, w, 0)
+    inv = kr.invert_affine(m.reshape(6))
+    rot90 = np.array([[0.0, 1.0, 0.0], [-1.0, 0.0, w - 1.0]])
+    hflip = np.array([[-1.0, 0.0, w - 1.0], [0.0, 1.0, 0.0]])
+    u8, f32 = torch.uint8, torch.float32
+    cases = []  # name, channels, source dtype, output dtype, op, output size
+    for c, st in ((1, u8), (2, u8), (1, f32), (3, f32)):
+        for dt in ((u8, f32) if st == u8 else (f32,)):
+            tag = f"c{c}_{'u8' if st == u8 else 'f32'}src_{'u8' if dt == u8 else 'f32'}"
+            cases.append((f"warp_{tag}", c, st, dt, "warp", (h, w)))
+            cases.append((f"resize1440_{tag}", c, st, dt, "resize", (1440, 2560)))
+    for c in (1, 2):
+        cases.append((f"rot90_c{c}_u8", c, u8, u8, "rot90", (w, h)))
+        cases.append((f"flip_c{c}_u8", c, u8, u8, "flip", (h, w)))
+    kern, total_px, total_ms = {}, 0, 0.0
+    for name, c, st, dt, op, (dh, dw) in cases:
+        img = wl.mixed_u8(h, w, c, seed=0)
+        if st == f32:
+            img = img.astype(np.float32)
+        srcs = [torch.from_numpy(img).cuda() for _ in range(copies)]
+        out = Rotating(torch, torch.empty((dh, dw, c), dtype=dt, device="cuda"))
+        if op == "warp":
+            def launch(s):
+                kr.warp_affine(s, out.next(), m, border=kr.CONSTANT)
+        elif op == "resize":
+            def launch(s):
+                kr.resize(s, out.next(), border=kr.REPLICATE)
+        else:
+            mp = rot90 if op == "rot90" else hflip
+            def launch(s, mp=mp):
+                kr.warp_affine(s, out.next(), mp, border=kr.CONSTANT)
+        for i in range(args.warmup):
+            launch(srcs[i % copies])
+        reps = max(args.steps, 20)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for i in range(reps):
+            launch(srcs[i % copies])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        esize = 4 if st == f32 else 1
+        if op == "warp":
+            src_bytes = warp_touched_bytes(h, w, dh, dw, inv, c=c, esize=esize)
+        elif op == "resize":
+            src_bytes = resize_touched_bytes(h, w, dh, dw, c=c, esize=esize)
+        else:
+            src_bytes = h * w * c * esize
+        alg = src_bytes + dh * dw * c * (4 if dt == f32 else 1)
+        gbps = alg / (ms * 1e-3) / 1e9
+        kern[name] = {"avg_us": round(ms * 1e3, 3), "alg_bytes": alg, "GBps": round(gbps, 1),
+                      "frac": round(gbps / HBM_PEAK_GBPS, 4), "Gpix_s": round(dh * dw / (ms * 1e-3) / 1e9, 2)}
+        total_px += dh * dw
+        total_ms += ms
+        del srcs, out
+    dom = max(kern, key=lambda n: kern[n]["avg_us"])
+    k = kern[dom]
+    return {
+        "metric": "output Gpixels/s (4K warp and 4K -> 1440p resize of 1- and 2-channel u8 sources and 1- and "
+                  "3-channel f32 sources, quarter turns and flips of 1- and 2-channel u8 sources)",
+        "value": round(total_px / (total_ms * 1e-3) / 1e9, 3), "unit": "Gpix/s", "ms_per_step": round(total_ms, 4),
+        "config": {"workload": "channels: 3840x2160 sources with 1 or 2 u8 channels, 1 or 3 f32 channels "
+                               "(mixed pattern), one launch of each case per step, cold sources",
+                   "px_per_step": total_px},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": k["frac"], "traffic": None, "alg_bytes_per_launch": k["alg_bytes"],
+                     "avg_launch_us": k["avg_us"]},
+        "kernels": kern,
+    }
+
+
 # ---------------------------------------------------------------- serving
 def bench_serve(args, torch, kr, wl):
     """10,000 requests (70 % resize, 30 % warp) with Poisson arrivals, sources
@@ -833,7 +915,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="4k", choices=["4k", "batch", "warpbatch", "serve", "ops", "warpseeds"])
+    ap.add_argument("--workload", default="4k",
+                    choices=["4k", "batch", "warpbatch", "serve", "ops", "warpseeds", "channels"])
     ap.add_argument("--cold-copies", type=int, default=16)
     ap.add_argument("--no-systems", action="store_true",
                     help="4k workload: skip the batched/served sub-records")
@@ -885,7 +968,7 @@ def main():
     copy_like_gbps = _copy_ceiling_like_kernels(torch, kr)
     if args.workload != "4k":
         fn = {"batch": bench_batch, "warpbatch": bench_warpbatch, "serve": bench_serve,
-              "ops": bench_ops, "warpseeds": bench_warpseeds}[args.workload]
+              "ops": bench_ops, "warpseeds": bench_warpseeds, "channels": bench_channels}[args.workload]
         r = fn(args, torch, kr, wl)
         out = {"metric": r.pop("metric"), "value": r.pop("value"), "unit": r.pop("unit")}
         out.update(common)
